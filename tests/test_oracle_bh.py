@@ -1,0 +1,165 @@
+"""Pins of the oracle's random streams and basin-hopping decisions
+(Algorithm Overview steps 1, 3, 4 and 5).
+
+Philox4x64-10 is checked against numpy's independent implementation and the
+all-zero known-answer vector; exp_bh against the C library's exp; the
+perturbation against exact rational arithmetic on numpy's random words; the
+select / Metropolis / adapt logic against hand-built energy tables.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_25938_amd.inputs import random_starts
+
+PERTURB, METROPOLIS = 3, 4
+
+
+def np_philox_block(ctr, key):
+    """numpy's Philox draws the block of counter+1, so hand it counter-1."""
+    c = [int(v) for v in ctr]
+    c[0] -= 1
+    i = 0
+    while c[i] < 0:  # borrow
+        c[i] += 2 ** 64
+        c[i + 1] -= 1
+        i += 1
+    bg = np.random.Philox(counter=np.array(c, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+def test_philox_known_answer_zero():
+    out = O.philox4x64_10([0, 0, 0, 0], [0, 0])
+    assert [f"{int(w):016x}" for w in out] == [
+        "16554d9eca36314c", "db20fe9d672d0fdc", "d7e772cee186176b", "7e68b68aec7ba23b"]
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        ctr = rng.integers(0, 2 ** 63, size=4, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        key = rng.integers(0, 2 ** 63, size=2, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        assert np.array_equal(O.philox4x64_10(ctr, key), np_philox_block(ctr, key))
+
+
+def test_exp_bh_against_libm():
+    zs = np.concatenate([-np.logspace(-12, np.log10(708), 4000), [-0.5, -1.0, -700.0, -1e-300]])
+    for z in zs:
+        e = O.exp_bh(z)
+        ref = math.exp(z)
+        assert abs(e - ref) <= 2 * math.ulp(ref), z
+    assert O.exp_bh(0.0) == 1.0
+    assert O.exp_bh(-0.0) == 1.0
+    assert O.exp_bh(-709.0) == 0.0
+    assert O.exp_bh(float("nan")) == 0.0
+    assert O.exp_bh(-math.inf) == 0.0
+
+
+def test_perturbation_exact():
+    _, x = random_starts([7], 3)
+    s, seed, chain, step, cand = 0.4, 123456789, 5, 17, 6
+    xc = O.perturb(x, s, seed, chain, step, cand)
+    n = x.shape[1]
+    for a in range(n):
+        for d in range(3):
+            k = 3 * a + d
+            w = int(np_philox_block([k // 4, chain, step, (PERTURB << 32) | cand], [seed, 0])[k % 4])
+            u = Fraction(w >> 11, 2 ** 53)
+            exact = Fraction(x[d, a]) + Fraction(s) * (2 * u - 1)
+            assert xc[d, a] == float(exact)
+    assert np.max(np.abs(xc - x)) <= s
+
+
+def test_perturbation_statistics():
+    _, x = random_starts([1000], 4)
+    xc = O.perturb(x, 0.4, 99, 0, 0, 0)
+    d = (xc - x).reshape(-1)
+    assert np.all(np.abs(d) <= 0.4)
+    assert abs(d.mean()) < 0.02
+    assert abs(d.var() - 0.4 ** 2 / 3) < 0.01  # uniform on [-s, s)
+
+
+def metropolis_u(seed, chain, step):
+    w = int(np_philox_block([0, chain, step, METROPOLIS << 32], [seed, 0])[0])
+    return (w >> 11) / 2.0 ** 53
+
+
+def test_selection_rules():
+    p = O.bh_params(1, 5, kT=0.8, seed=1)
+    st = O.chain_state(-10.0, 0.4)
+    sel, acc, imp, esel = O.bh_decide(st, p, 0, [-9.0, -11.0, np.nan, -11.0, -10.5])
+    assert sel == 1 and esel == -11.0 and acc == 1 and imp == 1  # ties -> lowest index
+    assert st.e_cur == -11.0 and st.win_accepts == 1 and st.e_best_acc == -11.0
+    assert st.e_best_seen == -11.0 and st.step_index == 1
+    sel, acc, imp, esel = O.bh_decide(st, p, 0, [np.nan, np.inf, np.nan, np.nan, np.nan])
+    assert sel == -1 and acc == 0 and math.isnan(esel)
+    assert st.step_index == 2 and st.e_cur == -11.0
+
+
+def test_metropolis_against_reference_draws():
+    seed, kT = 2024, 0.8
+    p = O.bh_params(1, 1, kT=kT, seed=seed, adapt_interval=1000)
+    n_acc = 0
+    for step in range(400):
+        dE = 0.05 + 0.002 * step
+        st = O.chain_state(-20.0, 0.4, step_index=step)
+        _, acc, _, _ = O.bh_decide(st, p, 3, [-20.0 + dE])
+        u = metropolis_u(seed, 3, step)
+        ref = math.exp(-dE / kT)
+        if abs(u - ref) > 1e-12:
+            assert acc == int(u < ref), step
+        n_acc += acc
+    assert 0 < n_acc < 400
+    # downhill and level moves are always accepted
+    st = O.chain_state(-20.0, 0.4)
+    assert O.bh_decide(st, p, 0, [-20.0])[1] == 1
+    # huge kT accepts everything, tiny kT rejects any uphill move
+    hot, cold = O.bh_params(1, 1, kT=1e12, seed=seed), O.bh_params(1, 1, kT=1e-12, seed=seed)
+    for step in range(50):
+        assert O.bh_decide(O.chain_state(0.0, 0.4, step_index=step), hot, 0, [1.0])[1] == 1
+        assert O.bh_decide(O.chain_state(0.0, 0.4, step_index=step), cold, 0, [1e-3])[1] == 0
+
+
+@pytest.mark.parametrize("accepts,expect", [(6, 1 / 0.9), (10, 1 / 0.9), (5, 1.0), (4, 0.9),
+                                            (0, 0.9)])
+def test_adaptation_window(accepts, expect):
+    p = O.bh_params(1, 1, kT=1e-300, seed=0)  # uphill always rejected
+    st = O.chain_state(0.0, 0.4)
+    for k in range(10):
+        down = k < accepts
+        O.bh_decide(st, p, 0, [st.e_cur - 1.0 if down else st.e_cur + 1.0])
+        if k < 9:
+            assert st.step == 0.4 and st.win_accepts == min(k + 1, accepts)
+    assert st.win_accepts == 0
+    assert st.step == (0.4 / 0.9 if expect > 1 else 0.4 * 0.9 if expect < 1 else 0.4)
+
+
+def test_lj13_chain_and_resume():
+    off, x = random_starts([13], 25102593801)
+    lp = O.lbfgs_params()
+    r = O.minimize(off, x, lp)
+    xcur = r["xyz"].copy()
+    p = O.bh_params(1, 8, kT=0.8, seed=25102593801)
+    st = [O.chain_state(r["energy"][0], 0.4)]
+    tr = O.bh_run(off, xcur, st, p, lp, 200)
+    assert st[0].e_best_acc == pytest.approx(-44.326801, abs=1e-6)  # soft pin: LJ13 is easy
+    e_best = tr["e_best"][0]
+    assert np.all(np.diff(e_best) <= 0.0)
+    acc = tr["accepted"][0].astype(bool)
+    assert np.array_equal(tr["e_cur"][0][acc], tr["e_trial"][0][acc])
+    steps = tr["step"][0]
+    changes = np.nonzero(np.diff(np.concatenate([[0.4], steps])))[0] + 1
+    assert np.all(changes % 10 == 0)
+    assert np.array_equal(np.nanmin(tr["ecand"][0], axis=1), tr["e_trial"][0])
+    # resume: 120 steps, then 80 more from the saved state == 200 in one go
+    xa = r["xyz"].copy()
+    sa = [O.chain_state(r["energy"][0], 0.4)]
+    ta = O.bh_run(off, xa, sa, p, lp, 120, cap=200)
+    tb = O.bh_run(off, xa, sa, p, lp, 80, cap=200)
+    assert np.array_equal(xa, xcur)
+    assert sa[0].e_cur == st[0].e_cur and sa[0].step == st[0].step
+    assert np.array_equal(np.concatenate([ta["e_trial"][0][:120], tb["e_trial"][0][120:]]),
+                          tr["e_trial"][0], equal_nan=True)

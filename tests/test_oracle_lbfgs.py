@@ -1,0 +1,185 @@
+"""Pins of the oracle's local minimiser (L-BFGS, Algorithm Overview step 2).
+
+Fixed points that do not come from the oracle: the unique minima of LJ2-LJ4;
+the icosahedral LJ13 minimum from a one-parameter closed form over its four
+distance classes (and the -44.326801 value of Wales & Doye 1997); the LJ38
+truncated octahedron (-173.928427, Wales & Doye 1997) built from the fcc
+lattice; the two-loop recursion against the dense BFGS inverse-Hessian update
+(Nocedal & Wright eq. 6.17); a scipy L-BFGS-B cross-check on an independent
+numpy energy.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+from oracle import oracle as O
+from paper_2510_25938_amd.inputs import random_starts
+
+PHI = (1 + math.sqrt(5)) / 2
+RMIN = 2.0 ** (1.0 / 6.0)
+
+
+def one(x):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return np.array([0, x.shape[1]], np.int32), x
+
+
+def icosahedron(R):
+    v = []
+    for a in (-1, 1):
+        for b in (-PHI, PHI):
+            v += [(0, a, b), (a, b, 0), (b, 0, a)]
+    v = np.array(v, dtype=float)
+    v *= R / np.linalg.norm(v[0])
+    return np.ascontiguousarray(np.vstack([np.zeros(3), v]).T)
+
+
+def lj13_closed_form(R):
+    """E of the centred icosahedron of radius R from its four distance classes."""
+    a = R * 4.0 / math.sqrt(10 + 2 * math.sqrt(5))  # edge length
+    v = lambda r: r ** -12 - r ** -6  # noqa: E731
+    return 4 * (12 * v(R) + 30 * v(a) + 30 * v(PHI * a) + 6 * v(2 * R))
+
+
+def truncated_octahedron38():
+    pts = [p for p in np.ndindex(5, 5, 5)]
+    pts = np.array(pts) - 2
+    keep = (pts.sum(axis=1) % 2 != 0) & ((pts ** 2).sum(axis=1) <= 5)
+    pts = pts[keep].astype(float)
+    assert len(pts) == 38
+    return np.ascontiguousarray((pts * RMIN / math.sqrt(2)).T)
+
+
+def numpy_energy_grad(flat):
+    """Independent vectorised E and dE/dx (AoS flat vector) for the scipy check."""
+    X = flat.reshape(-1, 3)
+    D = X[:, None, :] - X[None, :, :]
+    r2 = (D ** 2).sum(-1)
+    np.fill_diagonal(r2, 1.0)
+    ir6 = r2 ** -3
+    np.fill_diagonal(ir6, 0.0)
+    E = 2.0 * np.sum(ir6 * ir6 - ir6)
+    coef = (-48.0 * ir6 * ir6 + 24.0 * ir6) / r2
+    G = (coef[:, :, None] * D).sum(axis=1)
+    return E, G.reshape(-1)
+
+
+@pytest.mark.parametrize("n,emin", [(2, -1.0), (3, -3.0), (4, -6.0)])
+def test_unique_small_minima(n, emin):
+    for seed in range(20):
+        off, x = random_starts([n], 1000 + seed)
+        r = O.minimize(off, x)
+        assert r["status"][0] == O.CONVERGED
+        assert r["gnorm"][0] < 1e-6
+        assert r["energy"][0] == pytest.approx(emin, abs=1e-12)
+
+
+def test_lj13_icosahedron():
+    res = optimize.minimize_scalar(lj13_closed_form, bounds=(0.9, 1.3), method="bounded",
+                                   options={"xatol": 1e-12})
+    E_star = lj13_closed_form(res.x)
+    assert E_star == pytest.approx(-44.326801, abs=1e-6)
+    rng = np.random.default_rng(13)
+    for _ in range(5):
+        x = icosahedron(res.x) + rng.uniform(-0.05, 0.05, size=(3, 13))
+        off, x = one(x)
+        r = O.minimize(off, x)
+        assert r["status"][0] == O.CONVERGED
+        assert r["energy"][0] == pytest.approx(E_star, rel=1e-9)
+
+
+def test_lj38_truncated_octahedron():
+    off, x = one(truncated_octahedron38())
+    r = O.minimize(off, x)
+    assert r["status"][0] == O.CONVERGED
+    assert r["energy"][0] == pytest.approx(-173.928427, abs=1e-6)
+    X = r["xyz"].T
+    rad = np.sort(np.linalg.norm(X - X.mean(axis=0), axis=1))
+    # O_h shells: 6 + 8 + 24 atoms at three distinct radii
+    assert np.ptp(rad[:6]) < 1e-7 and np.ptp(rad[6:14]) < 1e-7 and np.ptp(rad[14:]) < 1e-7
+    assert rad[6] - rad[5] > 0.1 and rad[14] - rad[13] > 0.1
+
+
+def test_result_is_consistent_minimum():
+    off, x = random_starts([13, 20, 38], 77)
+    r = O.minimize(off, x)
+    E, g = O.energy_grad(off, r["xyz"])
+    assert np.array_equal(E, r["energy"])
+    for b in range(3):
+        gb = g[:, off[b]:off[b + 1]]
+        assert math.sqrt(float(np.sum(gb * gb))) < 1e-6
+    assert np.all(r["status"] == O.CONVERGED)
+    assert np.all(r["evals"] > r["iters"])
+
+
+def test_two_loop_matches_dense_bfgs():
+    rng = np.random.default_rng(3)
+    n = 5
+    dim = 3 * n
+    Q = rng.normal(size=(dim, dim))
+    A = Q @ Q.T + dim * np.eye(dim)  # SPD model Hessian
+    for hist in [0, 1, 4, 10]:
+        S = rng.normal(size=(hist, 3, n))
+        Y = np.stack([(A @ s.reshape(-1)).reshape(3, n) for s in S]) if hist else S
+        rho = np.array([1.0 / np.sum(s * y) for s, y in zip(S, Y)])
+        gamma = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])) if hist else 1.0
+        g = rng.normal(size=(3, n))
+        H = gamma * np.eye(dim)
+        for s, y, p in zip(S, Y, rho):  # oldest -> newest, eq. 6.17
+            s, y = s.reshape(-1), y.reshape(-1)
+            V = np.eye(dim) - p * np.outer(y, s)
+            H = V.T @ H @ V + p * np.outer(s, s)
+        d_ref = -(H @ g.reshape(-1))
+        d = O.two_loop(S, Y, rho, gamma, g).reshape(-1)
+        assert np.allclose(d, d_ref, rtol=1e-10, atol=1e-12 * np.abs(d_ref).max())
+
+
+def test_step_cap_and_armijo_first_iteration():
+    # Two atoms 0.3 apart: the steepest-descent direction is enormous, so the
+    # first step is capped at 0.2 per atom and must still lower the energy.
+    x = np.array([[0.0, 0.3, 2.0], [0.0, 0.0, 0.5], [0.0, 0.0, 0.0]])
+    off, x = one(x)
+    E0, _ = O.energy_grad(off, x)
+    r = O.minimize(off, x, O.lbfgs_params(max_iter=1))
+    assert r["status"][0] == O.MAXITER and r["iters"][0] == 1
+    disp = np.linalg.norm(r["xyz"] - x, axis=0)
+    assert disp.max() <= 0.2 * (1 + 1e-12)
+    assert r["energy"][0] < E0[0]
+
+
+def test_status_codes_and_degenerate_sizes():
+    off, x = random_starts([0, 1], 5)
+    r = O.minimize(off, x)
+    assert list(r["status"]) == [O.CONVERGED, O.CONVERGED]
+    assert list(r["iters"]) == [0, 0] and list(r["energy"]) == [0.0, 0.0]
+    off, x = one(np.zeros((3, 3)))
+    r = O.minimize(off, x)
+    assert r["status"][0] == O.NONFINITE
+    off, x = random_starts([38], 9)
+    r = O.minimize(off, x, O.lbfgs_params(max_iter=5))
+    assert r["status"][0] == O.MAXITER and r["iters"][0] == 5
+
+
+def test_quasi_newton_speed_on_lj38():
+    """L-BFGS converges far faster than steepest descent would (median < 600)."""
+    off, x = random_starts([38] * 12, 4242)
+    r = O.minimize(off, x)
+    assert np.all(r["status"] == O.CONVERGED)
+    assert np.median(r["iters"]) < 600
+    assert np.all(r["energy"] < -140.0)
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (4, 2), (13, 3)])
+def test_scipy_lbfgsb_same_minimum(n, seed):
+    if n == 13:
+        x0 = icosahedron(1.08) + np.random.default_rng(seed).uniform(-0.03, 0.03, (3, 13))
+    else:
+        _, x0 = random_starts([n], seed)
+    flat = np.ascontiguousarray(x0.T).reshape(-1)
+    res = optimize.minimize(numpy_energy_grad, flat, jac=True, method="L-BFGS-B",
+                            options={"gtol": 1e-10, "ftol": 1e-15, "maxiter": 10000})
+    off, x = one(x0)
+    r = O.minimize(off, x)
+    assert r["energy"][0] == pytest.approx(res.fun, rel=1e-9)
