@@ -1,0 +1,232 @@
+/*
+ * lj_bh.h - C ABI of liblj_bh.so, an MI355X (gfx950) library for the hot path
+ * of adaptive, parallel Basin Hopping on Lennard-Jones clusters
+ * (Carmona et al., arXiv 2510.25938).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers owned by the caller (HBM); scalar
+ *     descriptors (lj_batch, parameter structs, state/trace structs) are HOST
+ *     structs whose pointer members are device pointers unless noted.
+ *   - `stream` is a hipStream_t passed as void*.  Every call only enqueues
+ *     work on that stream and returns; results are valid once the stream has
+ *     been synchronised.  No call synchronises the host.
+ *   - No call allocates device memory.  Scratch memory is a caller-provided
+ *     workspace whose size comes from the matching *_workspace_bytes query;
+ *     the workspace must stay untouched until the enqueued work completes.
+ *   - Argument errors are detected on the host before anything is enqueued
+ *     and returned as a negative lj_status; lj_last_error() then describes
+ *     the failure (thread-local string).
+ *   - Numerical outcomes (convergence, line-search failure, overflow) are
+ *     per-cluster status codes (LJ_CONVERGED ...), never call errors.
+ *   - Reduced units throughout: sigma = epsilon = 1 (Eq. 1).
+ *
+ * Coordinate layout
+ *   A batch of B clusters of uneven size is described by offset[B+1], an
+ *   int32 device array of prefix sums: cluster b owns atoms
+ *   offset[b] .. offset[b+1]-1, N_b = offset[b+1] - offset[b] >= 0.
+ *   Coordinates and gradients are three planes of doubles
+ *   [3][total_atoms] = x plane, y plane, z plane.  The paper flattens one
+ *   cluster as [x0, y0, z0, x1, ...] (Methodology, Initial Structures and
+ *   Input); the planes are its per-component transpose, which makes every
+ *   HBM access by consecutive atoms contiguous.
+ *
+ * Precision modes
+ *   LJ_FP64   all arithmetic in FP64.  Per-atom sums run over partners in
+ *             ascending order and every sum over atoms is a pairwise
+ *             (balanced binary tree) sum over the atom index padded with
+ *             zeros to a power of two; FP64 results are therefore identical
+ *             bit for bit on every launch schedule.
+ *   LJ_MIXED  pair arithmetic (r^-6, r^-12, force factors) and per-tile
+ *             per-atom accumulation in FP32; per-cluster energy and all
+ *             dot products, L-BFGS curvature pairs and the Armijo test in
+ *             FP64; optionally followed by an FP64 polish.
+ */
+#ifndef LJ_BH_H
+#define LJ_BH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lj_status;
+#define LJ_OK 0
+#define LJ_E_ARG (-1)         /* invalid argument (null pointer, bad size, bad parameter) */
+#define LJ_E_HIP (-2)         /* a HIP runtime call failed (see lj_last_error)            */
+#define LJ_E_WORKSPACE (-3)   /* workspace missing or smaller than the query returned     */
+#define LJ_E_UNSUPPORTED (-4) /* cluster larger than the compiled limit, or no gfx950     */
+
+#define LJ_FP64 0
+#define LJ_MIXED 1
+
+/* Per-cluster status written by the minimiser. */
+#define LJ_CONVERGED 0 /* ||g||_2 < gtol                                               */
+#define LJ_MAXITER 1   /* iteration cap reached                                       */
+#define LJ_LSFAIL 2    /* line search failed from the steepest-descent direction      */
+#define LJ_NONFINITE 3 /* energy or gradient not finite (e.g. coincident atoms)       */
+#define LJ_SWITCHED 4  /* LJ_MIXED without polish: the FP32 phase met its tolerance
+                          or stopped making progress at FP32 resolution          */
+#define LJ_BADSIZE 5   /* the cluster's N from offset[] is negative or above max_n;
+                          the cluster was not processed                          */
+
+#define LJ_MAX_ATOMS_EVAL 4096 /* largest cluster for lj_energy_grad_batch        */
+#define LJ_MAX_ATOMS_MIN 1024  /* largest cluster for minimisation and BH         */
+#define LJ_MAX_M 10            /* largest L-BFGS history                          */
+#define LJ_MAX_CANDS 64        /* largest number of candidates per BH step        */
+
+/* A ragged batch.  offset is a device pointer; the other fields are host
+ * values that must agree with it: num = B >= 0, max_n >= every N_b,
+ * total_atoms = offset[B]. */
+typedef struct {
+    int32_t num;
+    const int32_t* offset;
+    int32_t max_n;
+    int64_t total_atoms;
+} lj_batch;
+
+/*
+ * lj_energy_grad_batch - Eq. (1) and its analytic gradient for every cluster.
+ *   E_b = 4 sum_{i<j} (r_ij^-12 - r_ij^-6),   g_i = dE/dx_i.
+ * Paper: Methodology, "Lennard-Jones Potential", Eq. (1); the gradient is the
+ * derivative of Eq. (1) that the L-BFGS-B minimiser consumes.
+ *   xyz     [3][total_atoms] device, read only.
+ *   energy  [num] device, written.
+ *   grad    [3][total_atoms] device, written; may be NULL (energy only).
+ *   precision LJ_FP64 or LJ_MIXED.
+ * N_b = 0 or 1 gives E = 0 and g = 0.  Coincident atoms give a non-finite E.
+ * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED (max_n > LJ_MAX_ATOMS_EVAL), LJ_E_HIP.
+ */
+lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double* energy,
+                               double* grad, int32_t precision, void* stream);
+
+/* L-BFGS parameters (host struct).  lj_lbfgs_defaults fills the defaults shown. */
+typedef struct {
+    int32_t m;                  /* stored (s, y) pairs, 0..LJ_MAX_M             [10]   */
+    double gtol;                /* stop when ||g||_2 < gtol                     [1e-6] */
+    int32_t max_iter;           /* accepted-step cap per phase                  [10000]*/
+    double max_step;            /* per-atom cap on the trial displacement       [0.2]  */
+    double c1;                  /* Armijo sufficient-decrease constant          [1e-4] */
+    int32_t max_ls;             /* backtracking halvings per line search        [30]   */
+    double curv_eps;            /* keep (s,y) only if s.y > curv_eps |s||y|     [1e-10]*/
+    double gtol_mixed_per_atom; /* LJ_MIXED: FP32 phase ends at
+                                   ||g|| < max(gtol, this*N)                    [1e-5] */
+    int32_t polish;             /* LJ_MIXED: run the FP64 polish                [1]    */
+    double ls_noise;            /* LJ_MIXED: Armijo allowance, relative to |E|  [5e-7] */
+} lj_lbfgs_params;
+
+void lj_lbfgs_defaults(lj_lbfgs_params* p);
+
+/* Workspace bytes needed by lj_bh_minimize_batch for this batch shape. */
+size_t lj_minimize_workspace_bytes(const lj_batch* batch, const lj_lbfgs_params* params,
+                                   int32_t precision);
+
+/*
+ * lj_bh_minimize_batch - local minimisation of every cluster of the batch in
+ * one persistent launch per cluster-size class (Algorithm Overview, step 2:
+ * n candidates minimised in parallel with L-BFGS-B; with no bounds this is
+ * L-BFGS: two-loop recursion, per-atom step cap, backtracking Armijo search).
+ *   xyz       [3][total_atoms] device: starts in, local minima out.
+ *   energy    [num] device: final FP64 energy.
+ *   gnorm     [num] device: final ||g||_2 (FP64).
+ *   iters     [num] device int32: accepted L-BFGS steps (both phases).
+ *   evals     [num] device int32: energy+gradient evaluations (both phases).
+ *   status    [num] device int32: LJ_CONVERGED ... LJ_SWITCHED.
+ *   xyz_switch [3][total_atoms] device or NULL: LJ_MIXED only, the point where
+ *             the FP32 phase ended (the polish starts there).
+ *   ws, ws_bytes  workspace of at least lj_minimize_workspace_bytes().
+ * The result of each cluster depends only on its own start and the
+ * parameters, never on the batch composition or the launch schedule.
+ * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED (max_n > LJ_MAX_ATOMS_MIN), LJ_E_WORKSPACE,
+ * LJ_E_HIP.
+ */
+lj_status lj_bh_minimize_batch(const lj_batch* batch, double* xyz, double* energy, double* gnorm,
+                               int32_t* iters, int32_t* evals, int32_t* status,
+                               double* xyz_switch, const lj_lbfgs_params* params,
+                               int32_t precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Basin-hopping parameters (host struct). */
+typedef struct {
+    int32_t cands;          /* n candidates per chain and step, 1..LJ_MAX_CANDS        */
+    double kT;              /* Metropolis temperature (paper: T = 1.0)                 */
+    int32_t adapt_interval; /* adapt the step size every this many steps (paper: 10)   */
+    double target_rate;     /* target acceptance rate (paper: 50%)                     */
+    double factor;          /* step /= factor above target, *= factor below       [0.9]*/
+    uint64_t seed;          /* key of the Philox4x64-10 streams                        */
+} lj_bh_params;
+
+/* Per-chain Markov-chain state; every member is a device array over chains
+ * (xyz_cur and xyz_best are planes [3][total_atoms] of the chains' batch).
+ * The caller initialises it: xyz_cur a local minimum, e_cur its energy,
+ * step the initial step size, win_accepts 0, step_index 0, e_best_seen +inf,
+ * e_best_acc = e_cur, xyz_best = xyz_cur. */
+typedef struct {
+    double* xyz_cur;
+    double* e_cur;
+    double* step;
+    int32_t* win_accepts;
+    int64_t* step_index;
+    double* e_best_seen; /* lowest selected trial energy so far (Fig. 2, running lowest) */
+    double* e_best_acc;  /* lowest accepted energy so far (Fig. 3)                        */
+    double* xyz_best;    /* structure of e_best_acc                                       */
+} lj_bh_state;
+
+/* Optional per-step trace, arrays [chains][capacity_steps] (e_cand:
+ * [chains][capacity_steps][cands]); row k is written by step k (0-based
+ * step_index) while k < capacity_steps.  Any member may be NULL. */
+typedef struct {
+    double* e_trial;    /* selected candidate energy, NaN if none finite            */
+    int8_t* accepted;   /* Metropolis decision                                       */
+    double* e_best;     /* e_best_seen after the step                                */
+    double* e_best_acc; /* e_best_acc after the step                                 */
+    double* e_cur;      /* e_cur after the step                                      */
+    double* step;       /* step size after the step's adaptation                     */
+    double* e_cand;     /* every candidate's energy (the values selection used)      */
+    int32_t capacity_steps;
+} lj_bh_trace;
+
+size_t lj_bh_workspace_bytes(const lj_batch* chains, const lj_bh_params* bh,
+                             const lj_lbfgs_params* params, int32_t precision);
+
+/*
+ * lj_bh_step - num_steps basin-hopping steps of every chain (Algorithm
+ * Overview, steps 1-5):
+ *   1. perturb: n copies of xyz_cur, each coordinate displaced by s(2u-1),
+ *      u uniform in [0,1) from Philox4x64-10 keyed (seed; chain, step,
+ *      candidate) - a cube of side 2s;
+ *   2. minimise all chains' candidates together (as lj_bh_minimize_batch);
+ *   3. select the lowest energy (first index on ties, non-finite ignored);
+ *   4. Metropolis: accept if dE <= 0 or u < exp(-dE/kT);
+ *   5. every adapt_interval steps: step /= factor if the window's accepted
+ *      count exceeds target_rate*interval, step *= factor if below.
+ * LJ_MIXED minimises candidates with the FP32 phase only (energies used for
+ * selection are FP64 re-evaluations at the FP32 endpoints) and polishes the
+ * accepted candidate in FP64 before it becomes the current structure.
+ * One step is captured once into a HIP graph per (shapes, pointers,
+ * parameters, stream) and replayed num_steps times; on a stream that is
+ * itself being captured the kernels are enqueued directly.
+ *   chains  batch descriptor of the chains (offset device, sizes host).
+ *   state   per-chain state (device arrays), updated in place.
+ *   trace   optional (NULL) per-step trace.
+ * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED, LJ_E_WORKSPACE, LJ_E_HIP.
+ */
+lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_bh_params* bh,
+                     const lj_lbfgs_params* params, int32_t precision, int32_t num_steps,
+                     const lj_bh_trace* trace, void* ws, size_t ws_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* lj_status_string(lj_status s);
+
+/* Description of the last error returned on this thread ("" if none). */
+const char* lj_last_error(void);
+
+/* ABI version of this header (incremented on any incompatible change). */
+#define LJ_ABI_VERSION 1
+int32_t lj_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJ_BH_H */

@@ -1,0 +1,464 @@
+// C ABI of liblj_bh.so: argument validation, workspace layout, launch
+// scheduling and the HIP-graph cache of the basin-hopping step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lj_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+lj_status fail(lj_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define LJ_HIP_TRY(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(LJ_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+struct DeviceInfo {
+    bool valid = false;
+    bool gfx950 = false;
+    int cus = 0;
+};
+
+std::mutex g_dev_mu;
+std::vector<DeviceInfo> g_dev;
+
+lj_status device_info(DeviceInfo& out) {
+    int dev = 0;
+    LJ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+    if (!g_dev[dev].valid) {
+        hipDeviceProp_t prop;
+        LJ_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        g_dev[dev].cus = prop.multiProcessorCount;
+        g_dev[dev].gfx950 = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        g_dev[dev].valid = true;
+    }
+    out = g_dev[dev];
+    if (!out.gfx950) return fail(LJ_E_UNSUPPORTED, "device %d is not gfx950", dev);
+    return LJ_OK;
+}
+
+lj_status check_batch(const lj_batch* b, int limit, const char* what) {
+    if (!b) return fail(LJ_E_ARG, "%s: batch is NULL", what);
+    if (b->num < 0) return fail(LJ_E_ARG, "%s: num = %d < 0", what, b->num);
+    if (b->num > 0 && !b->offset) return fail(LJ_E_ARG, "%s: offset is NULL", what);
+    if (b->max_n < 0) return fail(LJ_E_ARG, "%s: max_n = %d < 0", what, b->max_n);
+    if (b->max_n > limit)
+        return fail(LJ_E_UNSUPPORTED, "%s: max_n = %d exceeds the limit %d", what, b->max_n, limit);
+    if (b->total_atoms < 0 || b->total_atoms > INT32_MAX)
+        return fail(LJ_E_ARG, "%s: total_atoms = %lld out of range", what,
+                    (long long)b->total_atoms);
+    if ((int64_t)b->num * b->max_n < b->total_atoms)
+        return fail(LJ_E_ARG, "%s: total_atoms exceeds num * max_n", what);
+    return LJ_OK;
+}
+
+lj_status check_params(const lj_lbfgs_params* p) {
+    if (!p) return fail(LJ_E_ARG, "params is NULL");
+    if (p->m < 0 || p->m > LJ_MAX_M) return fail(LJ_E_ARG, "m = %d outside [0, %d]", p->m, LJ_MAX_M);
+    if (!(p->gtol > 0.0)) return fail(LJ_E_ARG, "gtol must be > 0");
+    if (p->max_iter < 0) return fail(LJ_E_ARG, "max_iter < 0");
+    if (!(p->max_step > 0.0)) return fail(LJ_E_ARG, "max_step must be > 0");
+    if (!(p->c1 > 0.0 && p->c1 < 1.0)) return fail(LJ_E_ARG, "c1 must be in (0, 1)");
+    if (p->max_ls < 1) return fail(LJ_E_ARG, "max_ls must be >= 1");
+    if (!(p->curv_eps >= 0.0)) return fail(LJ_E_ARG, "curv_eps must be >= 0");
+    if (!(p->gtol_mixed_per_atom >= 0.0)) return fail(LJ_E_ARG, "gtol_mixed_per_atom < 0");
+    if (!(p->ls_noise >= 0.0)) return fail(LJ_E_ARG, "ls_noise < 0");
+    return LJ_OK;
+}
+
+lj::LbfgsDev to_dev(const lj_lbfgs_params* p) {
+    lj::LbfgsDev d;
+    d.m = p->m;
+    d.gtol = p->gtol;
+    d.max_iter = p->max_iter;
+    d.max_step = p->max_step;
+    d.c1 = p->c1;
+    d.max_ls = p->max_ls;
+    d.curv_eps = p->curv_eps;
+    d.gtol_mixed_per_atom = p->gtol_mixed_per_atom;
+    d.polish = p->polish;
+    d.ls_noise = p->ls_noise;
+    return d;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace carve-up of one minimisation call.
+struct MinLayout {
+    size_t list = 0, cls = 0, queue = 0, hist = 0, total = 0;
+    int top_class = -1;
+    int grid[lj::kNumClasses] = {0, 0, 0, 0};
+};
+
+lj_status min_layout(int num, int max_n, int mixed, MinLayout& L) {
+    DeviceInfo di;
+    lj_status s = device_info(di);
+    if (s != LJ_OK) return s;
+    size_t off = 0;
+    L.list = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)(num > 0 ? num : 1));
+    L.cls = off;
+    off = align_up(off + sizeof(int32_t) * 2 * lj::kNumClasses);
+    L.queue = off;
+    off = align_up(off + sizeof(int32_t) * lj::kNumClasses);
+    L.top_class = lj::class_of(max_n < 0 ? 0 : max_n);
+    for (int c = 0; c <= L.top_class; ++c) {
+        int per_cu = 0;
+        LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, lj::minimize_kernel_for(mixed, c), lj::class_block(c), 0));
+        if (per_cu < 1) per_cu = 1;
+        long g = (long)per_cu * di.cus;
+        if (g > num) g = num;
+        if (g < 1) g = 1;
+        L.grid[c] = (int)g;
+    }
+    L.hist = off;
+    if (L.top_class >= 3) off = align_up(off + lj::class_hist_bytes_per_wg(3) * (size_t)L.grid[3]);
+    L.total = off;
+    return LJ_OK;
+}
+
+lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz, double* energy,
+                           double* gnorm, int32_t* iters, int32_t* evals, int32_t* status,
+                           double* xyz_switch, const lj::LbfgsDev& p, int mixed,
+                           const MinLayout& L, char* ws, hipStream_t st) {
+    if (b->num == 0) return LJ_OK;
+    lj::Plan plan;
+    plan.list = reinterpret_cast<int32_t*>(ws + L.list);
+    plan.cls = reinterpret_cast<int32_t*>(ws + L.cls);
+    plan.queue = reinterpret_cast<int32_t*>(ws + L.queue);
+    LJ_HIP_TRY(lj::launch_plan(b->offset, b->num, b->max_n, active, plan, status, st));
+    lj::MinArgs a;
+    a.offset = b->offset;
+    a.total = b->total_atoms;
+    a.xyz = xyz;
+    a.energy = energy;
+    a.gnorm = gnorm;
+    a.iters = iters;
+    a.evals = evals;
+    a.status = status;
+    a.xyz_switch = mixed ? xyz_switch : nullptr;
+    a.plan = plan;
+    a.p = p;
+    for (int c = L.top_class; c >= 0; --c) {  // largest clusters first
+        a.cls = c;
+        a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.grid[c], a, st));
+    }
+    return LJ_OK;
+}
+
+// Basin-hopping workspace carve-up.
+struct BhLayout {
+    size_t xc = 0, cand_off = 0, ce = 0, cg = 0, ci = 0, cv = 0, cs = 0, dec = 0, pe = 0, pg = 0,
+           pi = 0, pv = 0, ps = 0, min = 0, total = 0;
+    MinLayout cand_min, polish_min;
+    int64_t cand_total = 0;
+    int cand_num = 0;
+};
+
+lj_status bh_layout(const lj_batch* ch, const lj_bh_params* bh, int mixed, BhLayout& L) {
+    const int n = bh->cands;
+    L.cand_num = ch->num * n;
+    L.cand_total = ch->total_atoms * n;
+    if (L.cand_total > INT32_MAX) return fail(LJ_E_ARG, "candidate atom count exceeds int32");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes > 0 ? bytes : 1));
+        return at;
+    };
+    L.xc = take(sizeof(double) * 3 * (size_t)L.cand_total);
+    L.cand_off = take(sizeof(int32_t) * ((size_t)L.cand_num + 1));
+    L.ce = take(sizeof(double) * (size_t)L.cand_num);
+    L.cg = take(sizeof(double) * (size_t)L.cand_num);
+    L.ci = take(sizeof(int32_t) * (size_t)L.cand_num);
+    L.cv = take(sizeof(int32_t) * (size_t)L.cand_num);
+    L.cs = take(sizeof(int32_t) * (size_t)L.cand_num);
+    L.dec = take(sizeof(int32_t) * 2 * (size_t)ch->num);
+    L.pe = take(sizeof(double) * (size_t)ch->num);
+    L.pg = take(sizeof(double) * (size_t)ch->num);
+    L.pi = take(sizeof(int32_t) * (size_t)ch->num);
+    L.pv = take(sizeof(int32_t) * (size_t)ch->num);
+    L.ps = take(sizeof(int32_t) * (size_t)ch->num);
+    lj_status s = min_layout(L.cand_num, ch->max_n, mixed, L.cand_min);
+    if (s != LJ_OK) return s;
+    s = min_layout(ch->num, ch->max_n, 0, L.polish_min);
+    if (s != LJ_OK) return s;
+    L.min = off;
+    const size_t m = L.cand_min.total > L.polish_min.total ? L.cand_min.total : L.polish_min.total;
+    off = align_up(off + m);
+    L.total = off;
+    return LJ_OK;
+}
+
+lj_status check_bh(const lj_batch* ch, const lj_bh_params* bh) {
+    if (!bh) return fail(LJ_E_ARG, "bh params is NULL");
+    if (bh->cands < 1 || bh->cands > LJ_MAX_CANDS)
+        return fail(LJ_E_ARG, "cands = %d outside [1, %d]", bh->cands, LJ_MAX_CANDS);
+    if (!(bh->kT > 0.0)) return fail(LJ_E_ARG, "kT must be > 0");
+    if (bh->adapt_interval < 1) return fail(LJ_E_ARG, "adapt_interval must be >= 1");
+    if (!(bh->factor > 0.0)) return fail(LJ_E_ARG, "factor must be > 0");
+    if (!std::isfinite(bh->target_rate)) return fail(LJ_E_ARG, "target_rate not finite");
+    if ((int64_t)ch->num * bh->cands > INT32_MAX) return fail(LJ_E_ARG, "too many candidates");
+    return LJ_OK;
+}
+
+// One basin-hopping step enqueued on st.
+lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj::BhDev& p,
+                          const lj_lbfgs_params* lp, int mixed, const lj::BhTraceDev& tr,
+                          const BhLayout& L, char* ws, hipStream_t st) {
+    double* xc = reinterpret_cast<double*>(ws + L.xc);
+    int32_t* cand_off = reinterpret_cast<int32_t*>(ws + L.cand_off);
+    double* ce = reinterpret_cast<double*>(ws + L.ce);
+    int32_t* dec = reinterpret_cast<int32_t*>(ws + L.dec);
+    LJ_HIP_TRY(lj::launch_perturb(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, xc,
+                                  cand_off, st));
+    lj_batch cb;
+    cb.num = L.cand_num;
+    cb.offset = cand_off;
+    cb.max_n = ch->max_n;
+    cb.total_atoms = L.cand_total;
+    lj::LbfgsDev d = to_dev(lp);
+    if (mixed) d.polish = 0;  // only the accepted candidate is polished
+    lj_status r = enqueue_minimize(&cb, nullptr, xc, ce, reinterpret_cast<double*>(ws + L.cg),
+                                   reinterpret_cast<int32_t*>(ws + L.ci),
+                                   reinterpret_cast<int32_t*>(ws + L.cv),
+                                   reinterpret_cast<int32_t*>(ws + L.cs), nullptr, d, mixed,
+                                   L.cand_min, ws + L.min, st);
+    if (r != LJ_OK) return r;
+    LJ_HIP_TRY(lj::launch_decide(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, xc, ce, dec,
+                                 st));
+    double* pe = nullptr;
+    if (mixed) {
+        pe = reinterpret_cast<double*>(ws + L.pe);
+        lj::LbfgsDev d64 = to_dev(lp);
+        r = enqueue_minimize(ch, dec + ch->num, s.xyz_cur, pe, reinterpret_cast<double*>(ws + L.pg),
+                             reinterpret_cast<int32_t*>(ws + L.pi),
+                             reinterpret_cast<int32_t*>(ws + L.pv),
+                             reinterpret_cast<int32_t*>(ws + L.ps), nullptr, d64, 0, L.polish_min,
+                             ws + L.min, st);
+        if (r != LJ_OK) return r;
+    }
+    LJ_HIP_TRY(lj::launch_finalize(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, ce, dec, pe,
+                                   tr, st));
+    return LJ_OK;
+}
+
+// HIP-graph cache of one basin-hopping step, keyed by every argument byte.
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    int device;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+constexpr size_t kMaxGraphs = 16;
+
+template <typename T>
+void key_add(std::vector<unsigned char>& k, const T& v) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lj_status_string(lj_status s) {
+    switch (s) {
+        case LJ_OK: return "LJ_OK";
+        case LJ_E_ARG: return "LJ_E_ARG: invalid argument";
+        case LJ_E_HIP: return "LJ_E_HIP: HIP runtime error";
+        case LJ_E_WORKSPACE: return "LJ_E_WORKSPACE: workspace missing or too small";
+        case LJ_E_UNSUPPORTED: return "LJ_E_UNSUPPORTED: size above the compiled limit or not gfx950";
+    }
+    return "unknown lj_status";
+}
+
+const char* lj_last_error(void) { return g_err.c_str(); }
+
+int32_t lj_abi_version(void) { return LJ_ABI_VERSION; }
+
+void lj_lbfgs_defaults(lj_lbfgs_params* p) {
+    if (!p) return;
+    p->m = 10;
+    p->gtol = 1e-6;
+    p->max_iter = 10000;
+    p->max_step = 0.2;
+    p->c1 = 1e-4;
+    p->max_ls = 30;
+    p->curv_eps = 1e-10;
+    p->gtol_mixed_per_atom = 1e-5;
+    p->polish = 1;
+    p->ls_noise = 5e-7;
+}
+
+lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double* energy,
+                               double* grad, int32_t precision, void* stream) {
+    g_err.clear();
+    lj_status s = check_batch(batch, LJ_MAX_ATOMS_EVAL, "lj_energy_grad_batch");
+    if (s != LJ_OK) return s;
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return fail(LJ_E_ARG, "precision = %d is neither LJ_FP64 nor LJ_MIXED", precision);
+    if (batch->num == 0) return LJ_OK;
+    if (!energy) return fail(LJ_E_ARG, "energy is NULL");
+    if (batch->total_atoms > 0 && !xyz) return fail(LJ_E_ARG, "xyz is NULL");
+    DeviceInfo di;
+    s = device_info(di);
+    if (s != LJ_OK) return s;
+    LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, batch->max_n, batch->num,
+                                      batch->offset, batch->total_atoms, xyz, energy, grad,
+                                      static_cast<hipStream_t>(stream)));
+    return LJ_OK;
+}
+
+size_t lj_minimize_workspace_bytes(const lj_batch* batch, const lj_lbfgs_params* params,
+                                   int32_t precision) {
+    (void)params;
+    if (check_batch(batch, LJ_MAX_ATOMS_MIN, "lj_minimize_workspace_bytes") != LJ_OK) return 0;
+    MinLayout L;
+    if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L) != LJ_OK) return 0;
+    return L.total;
+}
+
+lj_status lj_bh_minimize_batch(const lj_batch* batch, double* xyz, double* energy, double* gnorm,
+                               int32_t* iters, int32_t* evals, int32_t* status,
+                               double* xyz_switch, const lj_lbfgs_params* params,
+                               int32_t precision, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    lj_status s = check_batch(batch, LJ_MAX_ATOMS_MIN, "lj_bh_minimize_batch");
+    if (s != LJ_OK) return s;
+    if ((s = check_params(params)) != LJ_OK) return s;
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return fail(LJ_E_ARG, "precision = %d is neither LJ_FP64 nor LJ_MIXED", precision);
+    if (batch->num == 0) return LJ_OK;
+    if (!energy || !gnorm || !iters || !evals || !status)
+        return fail(LJ_E_ARG, "an output array is NULL");
+    if (batch->total_atoms > 0 && !xyz) return fail(LJ_E_ARG, "xyz is NULL");
+    MinLayout L;
+    if ((s = min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L)) != LJ_OK) return s;
+    if (!ws || ws_bytes < L.total)
+        return fail(LJ_E_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, L.total);
+    return enqueue_minimize(batch, nullptr, xyz, energy, gnorm, iters, evals, status, xyz_switch,
+                            to_dev(params), precision == LJ_MIXED, L, static_cast<char*>(ws),
+                            static_cast<hipStream_t>(stream));
+}
+
+size_t lj_bh_workspace_bytes(const lj_batch* chains, const lj_bh_params* bh,
+                             const lj_lbfgs_params* params, int32_t precision) {
+    (void)params;
+    if (check_batch(chains, LJ_MAX_ATOMS_MIN, "lj_bh_workspace_bytes") != LJ_OK) return 0;
+    if (check_bh(chains, bh) != LJ_OK) return 0;
+    BhLayout L;
+    if (bh_layout(chains, bh, precision == LJ_MIXED, L) != LJ_OK) return 0;
+    return L.total;
+}
+
+lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_bh_params* bh,
+                     const lj_lbfgs_params* params, int32_t precision, int32_t num_steps,
+                     const lj_bh_trace* trace, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    lj_status s = check_batch(chains, LJ_MAX_ATOMS_MIN, "lj_bh_step");
+    if (s != LJ_OK) return s;
+    if ((s = check_params(params)) != LJ_OK) return s;
+    if ((s = check_bh(chains, bh)) != LJ_OK) return s;
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return fail(LJ_E_ARG, "precision = %d is neither LJ_FP64 nor LJ_MIXED", precision);
+    if (num_steps < 0) return fail(LJ_E_ARG, "num_steps < 0");
+    if (!state) return fail(LJ_E_ARG, "state is NULL");
+    if (chains->num == 0 || num_steps == 0) return LJ_OK;
+    if (!state->xyz_cur || !state->e_cur || !state->step || !state->win_accepts ||
+        !state->step_index || !state->e_best_seen || !state->e_best_acc || !state->xyz_best)
+        return fail(LJ_E_ARG, "a state array is NULL");
+    if (trace && trace->capacity_steps < 0) return fail(LJ_E_ARG, "trace capacity < 0");
+    const int mixed = precision == LJ_MIXED;
+    BhLayout L;
+    if ((s = bh_layout(chains, bh, mixed, L)) != LJ_OK) return s;
+    if (!ws || ws_bytes < L.total)
+        return fail(LJ_E_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, L.total);
+
+    lj::BhStateDev sd{state->xyz_cur, state->e_cur,       state->step,       state->win_accepts,
+                      state->step_index, state->e_best_seen, state->e_best_acc, state->xyz_best};
+    lj::BhDev pd{bh->cands, bh->kT, bh->adapt_interval, bh->target_rate, bh->factor, bh->seed};
+    lj::BhTraceDev td{};
+    if (trace)
+        td = lj::BhTraceDev{trace->e_trial, trace->accepted, trace->e_best,         trace->e_best_acc,
+                            trace->e_cur,   trace->step,     trace->e_cand,         trace->capacity_steps};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st) LJ_HIP_TRY(hipStreamIsCapturing(st, &cap));
+    if (!st || cap != hipStreamCaptureStatusNone) {
+        for (int k = 0; k < num_steps; ++k)
+            if ((s = enqueue_bh_step(chains, sd, pd, params, mixed, td, L, w, st)) != LJ_OK) return s;
+        return LJ_OK;
+    }
+
+    int dev = 0;
+    LJ_HIP_TRY(hipGetDevice(&dev));
+    std::vector<unsigned char> key;
+    key_add(key, *chains);
+    key_add(key, sd);
+    key_add(key, pd);
+    key_add(key, *params);
+    key_add(key, precision);
+    key_add(key, td);
+    key_add(key, ws);
+    key_add(key, ws_bytes);
+    key_add(key, st);
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto& e : g_graphs)
+            if (e.device == dev && e.key == key) exec = e.exec;
+    }
+    if (!exec) {
+        LJ_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        s = enqueue_bh_step(chains, sd, pd, params, mixed, td, L, w, st);
+        hipGraph_t graph = nullptr;
+        hipError_t ec = hipStreamEndCapture(st, &graph);
+        if (s != LJ_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return s;
+        }
+        if (ec != hipSuccess) return fail(LJ_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ec != hipSuccess) return fail(LJ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ec));
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kMaxGraphs) {
+            hipGraphExecDestroy(g_graphs.front().exec);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(GraphEntry{key, dev, exec});
+    }
+    for (int k = 0; k < num_steps; ++k) LJ_HIP_TRY(hipGraphLaunch(exec, st));
+    return LJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+// Device building blocks for gfx950: team reductions in a fixed tree order,
+// the LDS-staged Lennard-Jones pair loops (FP64 and FP32), Philox4x64-10 and
+// the deterministic exp used by the Metropolis test.
+//
+// A "team" is the W wavefronts (64 lanes each) of one workgroup that work on
+// one cluster.  Atom i of a cluster lives in thread t = i mod T, slot
+// a = i / T (T = 64 W); each thread keeps its A slots in registers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lj {
+
+constexpr int kWave = 64;
+constexpr int kMaxM = 10;   // L-BFGS history held per cluster (LJ_MAX_M)
+constexpr int kTileJ = 64;  // FP32 partner tile before a per-atom FP64 flush
+
+// ---------------------------------------------------------------------------
+// Wave-uniform broadcast of a value that every lane already holds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double uniform(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    b.x = __builtin_amdgcn_readfirstlane(b.x);
+    b.y = __builtin_amdgcn_readfirstlane(b.y);
+    return *reinterpret_cast<double*>(&b);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// Sum over the 64 lanes by an xor butterfly.  Step k adds the value of the
+// lane 2^k away, so after six steps every lane holds the balanced binary tree
+// sum over the lane index (IEEE addition is commutative, so the two lanes of
+// each pair compute identical bits).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = v + __shfl_xor(v, m, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = fmax(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+// Balanced tree over K values (K a power of two): ((r0+r1)+(r2+r3))+...
+template <int K>
+__device__ __forceinline__ double tree(const double* r) {
+    if constexpr (K == 1) {
+        return r[0];
+    } else {
+        return tree<K / 2>(r) + tree<K / 2>(r + K / 2);
+    }
+}
+
+// Team reduction scratch in LDS: two alternating banks of NV x W doubles.
+// One barrier per reduction: a bank is rewritten only two reductions later,
+// and every thread has passed the intermediate reduction's barrier (after
+// reading this bank) before that happens.
+template <int W, int NVMAX>
+struct TeamScratch {
+    double v[2][NVMAX][W];
+};
+
+// Reduce NV sums over the whole cluster.  vals[k][a] is this thread's value
+// for atom slot a; the result for k is tree_a( tree_w( wave_sum ) ), i.e. the
+// pairwise sum over the atom index i = a*T + w*64 + lane padded to a power of
+// two.  Every thread of the team receives every result.
+template <int W, int A, int NV, int NVMAX>
+__device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV],
+                                         TeamScratch<W, NVMAX>& sc, int& bank) {
+    static_assert(NV * A <= NVMAX, "scratch too small");
+    double ws[NV][A];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int a = 0; a < A; ++a) ws[k][a] = wave_sum(vals[k][a]);
+    if constexpr (W == 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double r[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) r[a] = uniform(ws[k][a]);
+            out[k] = tree<A>(r);
+        }
+    } else {
+        const int w = threadIdx.x / kWave;
+        const int lane = threadIdx.x % kWave;
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int a = 0; a < A; ++a) sc.v[bank][k * A + a][w] = ws[k][a];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double r[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                double rw[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) rw[q] = sc.v[bank][k * A + a][q];
+                r[a] = tree<W>(rw);
+            }
+            out[k] = uniform(tree<A>(r));  // identical in every lane
+        }
+        bank ^= 1;
+    }
+}
+
+template <int W, int A, int NVMAX>
+__device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<W, NVMAX>& sc,
+                                           int& bank) {
+    double m = vals[0];
+#pragma unroll
+    for (int a = 1; a < A; ++a) m = fmax(m, vals[a]);
+    m = wave_max(m);
+    if constexpr (W == 1) {
+        return uniform(m);
+    } else {
+        const int w = threadIdx.x / kWave;
+        if (threadIdx.x % kWave == 0) sc.v[bank][0][w] = m;
+        __syncthreads();
+        double r = sc.v[bank][0][0];
+#pragma unroll
+        for (int q = 1; q < W; ++q) r = fmax(r, sc.v[bank][0][q]);
+        bank ^= 1;
+        return uniform(r);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (1) pair loops.  pos holds the cluster's coordinates in LDS as
+// (x, y, z, pad); every lane reads the same partner j (LDS broadcast).
+// Per atom i: e_i = sum_{j != i, ascending j} (s6^2 - s6) with q = 1/r^2,
+// s6 = q^3, and g_i = sum_{j != i} q s6 (24 - 48 s6) (x_i - x_j).
+// ---------------------------------------------------------------------------
+
+// FP64: every operation rounded as written, so the sums are reproducible.
+template <int A, int T>
+__device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ pos,
+                                           const double (&x)[3][A], double (&e)[A],
+                                           double (&g)[3][A]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        e[a] = 0.0;
+        g[0][a] = g[1][a] = g[2][a] = 0.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        const double4 pj = pos[j];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const double dx = x[0][a] - pj.x;
+            const double dy = x[1][a] - pj.y;
+            const double dz = x[2][a] - pj.z;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double q = 1.0 / r2;
+            const double s6 = (q * q) * q;
+            const double te = fma(s6, s6, -s6);
+            const double f = (q * s6) * fma(-48.0, s6, 24.0);
+            const bool self = (j == a * T + t);
+            e[a] = self ? e[a] : e[a] + te;
+            g[0][a] = self ? g[0][a] : fma(f, dx, g[0][a]);
+            g[1][a] = self ? g[1][a] : fma(f, dy, g[1][a]);
+            g[2][a] = self ? g[2][a] : fma(f, dz, g[2][a]);
+        }
+    }
+}
+
+// FP32 pair arithmetic and FP32 accumulation over tiles of kTileJ partners;
+// each tile's per-atom partial sums are added into FP64 accumulators.
+template <int A, int T>
+__device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ pos,
+                                            const double (&x)[3][A], double (&e)[A],
+                                            double (&g)[3][A]) {
+    const int t = threadIdx.x;
+    float xf[3][A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        e[a] = 0.0;
+        g[0][a] = g[1][a] = g[2][a] = 0.0;
+        xf[0][a] = (float)x[0][a];
+        xf[1][a] = (float)x[1][a];
+        xf[2][a] = (float)x[2][a];
+    }
+    for (int j0 = 0; j0 < n; j0 += kTileJ) {
+        const int j1 = min(n, j0 + kTileJ);
+        float te[A], tg[3][A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) te[a] = tg[0][a] = tg[1][a] = tg[2][a] = 0.0f;
+        for (int j = j0; j < j1; ++j) {
+            const float4 pj = pos[j];
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                const float dx = xf[0][a] - pj.x;
+                const float dy = xf[1][a] - pj.y;
+                const float dz = xf[2][a] - pj.z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float q = __builtin_amdgcn_rcpf(r2);
+                const float s6 = (q * q) * q;
+                const float ee = fmaf(s6, s6, -s6);
+                const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+                const bool self = (j == a * T + t);
+                te[a] = self ? te[a] : te[a] + ee;
+                tg[0][a] = self ? tg[0][a] : fmaf(f, dx, tg[0][a]);
+                tg[1][a] = self ? tg[1][a] : fmaf(f, dy, tg[1][a]);
+                tg[2][a] = self ? tg[2][a] : fmaf(f, dz, tg[2][a]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            e[a] += (double)te[a];
+            g[0][a] += (double)tg[0][a];
+            g[1][a] += (double)tg[1][a];
+            g[2][a] += (double)tg[2][a];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128-bit multiplies; the key is bumped by the Weyl constants between
+// rounds.
+// ---------------------------------------------------------------------------
+struct U64x4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                               uint64_t c3, uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    U64x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+constexpr uint64_t kPurposePerturb = 3;
+constexpr uint64_t kPurposeMetropolis = 4;
+
+// Top 53 bits of a random word as a double in [0, 1).
+__device__ __forceinline__ double unit_double(uint64_t w) {
+    return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// exp(z) for z <= 0 by Cody-Waite reduction z = k ln2 + r (ln2 split into a
+// high part with 32 trailing zero bits and a low part) and the degree-13
+// Taylor polynomial of e^r in Horner form (|r| <= ln2/2, truncation error
+// below 2^-53), scaled by 2^k; 0 below -708 and for NaN.  Every operation is
+// a correctly rounded IEEE operation, so the result does not depend on the
+// device.
+__device__ __forceinline__ double exp_metropolis(double z) {
+    if (!(z >= -708.0)) return 0.0;
+    const double kf = rint(z * 1.4426950408889634);
+    double r = fma(-kf, 6.93147180369123816490e-01, z);
+    r = fma(-kf, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)kf);
+}
+
+}  // namespace lj

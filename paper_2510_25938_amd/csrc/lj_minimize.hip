@@ -1,0 +1,676 @@
+// Batched energy+gradient and the persistent L-BFGS minimiser (gfx950).
+//
+// Energy: Eq. (1) of Carmona et al.; minimiser: the paper's L-BFGS-B with no
+// active bounds, i.e. L-BFGS (two-loop recursion of Nocedal & Wright,
+// Alg. 7.4) with a per-atom step cap and a backtracking Armijo line search
+// (Algorithm Overview, step 2).
+//
+// One workgroup ("team", W wavefronts) owns one cluster at a time and runs
+// its whole minimisation on chip: coordinates are staged in LDS for the pair
+// loop, all reductions go through wavefront butterflies and (for W > 1) a
+// small LDS exchange, and for N <= 256 the m (s, y) history pairs stay in
+// registers.  Teams are persistent: they claim clusters from a queue that
+// lists the batch by N descending (longest first), one launch per size class.
+#include <hip/hip_runtime.h>
+
+#include "lj_kernels.hpp"
+
+namespace lj {
+
+// ---------------------------------------------------------------------------
+// Team: LDS buffers and the collective operations of one workgroup.
+// ---------------------------------------------------------------------------
+template <int W, int A>
+struct Team {
+    static constexpr int T = kWave * W;
+    static constexpr int NVMAX = 3 * A;
+    double4* pos64;
+    float4* pos32;
+    TeamScratch<W, NVMAX>* sc;
+    int bank;
+    int n;
+
+    __device__ __forceinline__ bool active(int a) const { return a * T + (int)threadIdx.x < n; }
+
+    __device__ __forceinline__ double dot(const double (&u)[3][A], const double (&v)[3][A]) {
+        double p[1][A], o[1];
+#pragma unroll
+        for (int a = 0; a < A; ++a) p[0][a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
+        team_sum<W, A, 1, NVMAX>(p, o, *sc, bank);
+        return o[0];
+    }
+
+    // (u.v, v.v, u.u) in one reduction.
+    __device__ __forceinline__ void dot3(const double (&u)[3][A], const double (&v)[3][A], double& uv,
+                                         double& vv, double& uu) {
+        double p[3][A], o[3];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            p[0][a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
+            p[1][a] = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
+            p[2][a] = fma(u[2][a], u[2][a], fma(u[1][a], u[1][a], u[0][a] * u[0][a]));
+        }
+        team_sum<W, A, 3, NVMAX>(p, o, *sc, bank);
+        uv = o[0];
+        vv = o[1];
+        uu = o[2];
+    }
+
+    // Largest per-atom squared norm of v.
+    __device__ __forceinline__ double max_atom_norm2(const double (&v)[3][A]) {
+        double m[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) m[a] = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
+        return team_max<W, A, NVMAX>(m, *sc, bank);
+    }
+
+    // E and g at x.  F32: FP32 pair arithmetic and tile sums, FP64 totals.
+    template <bool F32>
+    __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
+        __syncthreads();  // previous readers of the position buffer are done
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int i = a * T + threadIdx.x;
+            if (i < n) {
+                if constexpr (F32)
+                    pos32[i] = make_float4((float)x[0][a], (float)x[1][a], (float)x[2][a], 0.0f);
+                else
+                    pos64[i] = make_double4(x[0][a], x[1][a], x[2][a], 0.0);
+            }
+        }
+        __syncthreads();
+        double e[1][A], o[1];
+        if constexpr (F32)
+            pairs_mixed<A, T>(n, pos32, x, e[0], g);
+        else
+            pairs_fp64<A, T>(n, pos64, x, e[0], g);
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+            if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
+        team_sum<W, A, 1, NVMAX>(e, o, *sc, bank);
+        return 2.0 * o[0];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// L-BFGS history.  rho is kept by age (slot 0 = newest) in registers; the
+// vectors either by age in registers (HREG, shifted on every push) or in a
+// global ring owned by the persistent workgroup.
+// ---------------------------------------------------------------------------
+template <int W, int A, bool HREG>
+struct History;
+
+template <int W, int A>
+struct History<W, A, true> {
+    double S[kMaxM][3][A];
+    double Y[kMaxM][3][A];
+    double rho[kMaxM];
+    int hist = 0;
+    double gamma = 1.0;
+
+    __device__ __forceinline__ void init(double*, int) { hist = 0; gamma = 1.0; }
+    __device__ __forceinline__ void clear() { hist = 0; }
+
+    __device__ __forceinline__ void push(const double (&s)[3][A], const double (&y)[3][A], double r,
+                                         double gam, int m) {
+#pragma unroll
+        for (int k = kMaxM - 1; k > 0; --k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < A; ++a) {
+                    S[k][c][a] = S[k - 1][c][a];
+                    Y[k][c][a] = Y[k - 1][c][a];
+                }
+            rho[k] = rho[k - 1];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                S[0][c][a] = s[c][a];
+                Y[0][c][a] = y[c][a];
+            }
+        rho[0] = r;
+        gamma = gam;
+        hist = hist < m ? hist + 1 : m;
+    }
+
+    // r <- H r (r holds g on entry).
+    __device__ __forceinline__ void apply(Team<W, A>& tm, double (&r)[3][A]) {
+        const int h = uniform(hist);
+        double al[kMaxM];
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k) {
+            if (k < h) {
+                const double a = rho[k] * tm.dot(S[k], r);
+                al[k] = a;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) r[c][q] = fma(-a, Y[k][c][q], r[c][q]);
+            }
+        }
+        if (h > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < A; ++q) r[c][q] = gamma * r[c][q];
+        }
+#pragma unroll
+        for (int k = kMaxM - 1; k >= 0; --k) {
+            if (k < h) {
+                const double b = rho[k] * tm.dot(Y[k], r);
+                const double w = al[k] - b;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) r[c][q] = fma(w, S[k][c][q], r[c][q]);
+            }
+        }
+    }
+};
+
+template <int W, int A>
+struct History<W, A, false> {
+    static constexpr int T = kWave * W;
+    double* base;  // this workgroup's ring: S slots then Y slots, [slot][3][A][T]
+    double rho[kMaxM];
+    int hist = 0;
+    int newest = -1;
+    int m = 1;
+    double gamma = 1.0;
+
+    __device__ __forceinline__ double* vec(int slot, bool isY) const {
+        return base + ((size_t)((isY ? kMaxM : 0) + slot) * 3 * A) * T + threadIdx.x;
+    }
+    __device__ __forceinline__ void init(double* b, int mm) {
+        base = b;
+        m = mm > 0 ? mm : 1;
+        hist = 0;
+        newest = -1;
+        gamma = 1.0;
+    }
+    __device__ __forceinline__ void clear() { hist = 0; }
+
+    __device__ __forceinline__ void push(const double (&s)[3][A], const double (&y)[3][A], double r,
+                                         double gam, int mm) {
+        newest = (newest + 1) % m;
+        double* ps = vec(newest, false);
+        double* py = vec(newest, true);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                ps[(c * A + a) * T] = s[c][a];
+                py[(c * A + a) * T] = y[c][a];
+            }
+#pragma unroll
+        for (int k = kMaxM - 1; k > 0; --k) rho[k] = rho[k - 1];
+        rho[0] = r;
+        gamma = gam;
+        hist = hist < mm ? hist + 1 : mm;
+    }
+
+    __device__ __forceinline__ void apply(Team<W, A>& tm, double (&r)[3][A]) {
+        const int h = uniform(hist);
+        double al[kMaxM];
+        double v[3][A];
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k) {
+            if (k < h) {
+                const int slot = (newest - k + m) % m;
+                const double* ps = vec(slot, false);
+                const double* py = vec(slot, true);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) v[c][q] = ps[(c * A + q) * T];
+                const double a = rho[k] * tm.dot(v, r);
+                al[k] = a;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) r[c][q] = fma(-a, py[(c * A + q) * T], r[c][q]);
+            }
+        }
+        if (h > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < A; ++q) r[c][q] = gamma * r[c][q];
+        }
+#pragma unroll
+        for (int k = kMaxM - 1; k >= 0; --k) {
+            if (k < h) {
+                const int slot = (newest - k + m) % m;
+                const double* ps = vec(slot, false);
+                const double* py = vec(slot, true);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) v[c][q] = py[(c * A + q) * T];
+                const double b = rho[k] * tm.dot(v, r);
+                const double w = al[k] - b;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int q = 0; q < A; ++q) r[c][q] = fma(w, ps[(c * A + q) * T], r[c][q]);
+            }
+        }
+    }
+};
+
+// Phase outcomes (LJ_* statuses, plus the FP32 phase's stall exit).
+constexpr int kStall = 100;
+
+// One L-BFGS run from x (history cleared).  On return x, g, E hold the last
+// accepted iterate.  F32 selects the FP32 pair arithmetic, the Armijo noise
+// allowance and the stall exit of the mixed path's first phase.
+template <bool F32, int W, int A, bool HREG>
+__device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][A],
+                         double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
+                         const LbfgsDev& p, double gtol, int max_iter) {
+    double d[3][A], xt[3][A], gt[3][A];
+    H.clear();
+    E = tm.template eval<F32>(x, g);
+    ++evals;
+    int it = 0;
+    int stall = 0;
+    const double ms2 = p.max_step * p.max_step;
+    for (;;) {
+        double gg;
+        {
+            double p1[1][A], o[1];
+#pragma unroll
+            for (int a = 0; a < A; ++a) p1[0][a] = fma(g[2][a], g[2][a], fma(g[1][a], g[1][a], g[0][a] * g[0][a]));
+            team_sum<W, A, 1, Team<W, A>::NVMAX>(p1, o, *tm.sc, tm.bank);
+            gg = o[0];
+        }
+        gnorm = sqrt(gg);
+        if (!isfinite(E) || !isfinite(gg)) {
+            iters += it;
+            return LJ_NONFINITE;
+        }
+        if (gnorm < gtol) {
+            iters += it;
+            return LJ_CONVERGED;
+        }
+        if (it >= max_iter) {
+            iters += it;
+            return LJ_MAXITER;
+        }
+        // d = -H g
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) d[c][a] = g[c][a];
+        H.apply(tm, d);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) d[c][a] = -d[c][a];
+        double gd = tm.dot(g, d);
+        if (uniform(H.hist) > 0 && !(gd < 0.0)) {
+            H.clear();
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < A; ++a) d[c][a] = -g[c][a];
+            gd = tm.dot(g, d);
+        }
+        const double dmax2 = tm.max_atom_norm2(d);
+        if (dmax2 > ms2) {
+            const double sc = p.max_step / sqrt(dmax2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < A; ++a) d[c][a] = d[c][a] * sc;
+            gd = tm.dot(g, d);
+        }
+        // backtracking Armijo line search
+        double alpha = 1.0, Et = 0.0;
+        bool ok = false;
+        for (int ls = 0; ls < p.max_ls; ++ls) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < A; ++a) xt[c][a] = fma(alpha, d[c][a], x[c][a]);
+            Et = tm.template eval<F32>(xt, gt);
+            ++evals;
+            double rhs = fma(p.c1 * alpha, gd, E);
+            if constexpr (F32) rhs = rhs + p.ls_noise * fabs(E);
+            if (Et <= rhs) {
+                ok = true;
+                break;
+            }
+            alpha = alpha * 0.5;
+        }
+        if (!ok) {
+            if (uniform(H.hist) > 0) {
+                H.clear();
+                continue;
+            }
+            iters += it;
+            return LJ_LSFAIL;
+        }
+        // s = xt - x (into d), y = gt - g (into g)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                d[c][a] = xt[c][a] - x[c][a];
+                g[c][a] = gt[c][a] - g[c][a];
+            }
+        double sy, yy, ss;
+        tm.dot3(d, g, sy, yy, ss);
+        if (p.m > 0 && sy > p.curv_eps * sqrt(ss * yy)) H.push(d, g, 1.0 / sy, sy / yy, p.m);
+        if constexpr (F32) stall = (Et < E) ? 0 : stall + 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                x[c][a] = xt[c][a];
+                g[c][a] = gt[c][a];
+            }
+        E = Et;
+        ++it;
+        if constexpr (F32) {
+            if (stall >= 5) {
+                iters += it;
+                return kStall;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent minimiser kernel: one launch per size class.
+// ---------------------------------------------------------------------------
+template <int MIXED, int W, int A, bool HREG>
+__global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
+    constexpr int T = kWave * W;
+    __shared__ double4 pos_buf[T * A];
+    __shared__ TeamScratch<W, 3 * A> scratch;
+    __shared__ int claim;
+
+    Team<W, A> tm;
+    tm.pos64 = pos_buf;
+    tm.pos32 = reinterpret_cast<float4*>(pos_buf);
+    tm.sc = &scratch;
+    tm.bank = 0;
+    History<W, A, HREG> H;
+    constexpr size_t kHistPerWG = (size_t)2 * kMaxM * 3 * A * T;
+    H.init(args.hist ? args.hist + kHistPerWG * blockIdx.x : nullptr, args.p.m);
+
+    const int start = args.plan.cls[args.cls];
+    const int count = args.plan.cls[kNumClasses + args.cls];
+    const int64_t total = args.total;
+    for (;;) {
+        if (threadIdx.x == 0) claim = atomicAdd(&args.plan.queue[args.cls], 1);
+        __syncthreads();
+        const int idx = claim;
+        __syncthreads();
+        if (idx >= count) break;
+        const int b = args.plan.list[start + idx];
+        const int o = args.offset[b];
+        const int n = args.offset[b + 1] - o;
+        tm.n = n;  // the plan guarantees 0 <= n <= T*A
+
+        double x[3][A], g[3][A];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                const int i = a * T + threadIdx.x;
+                x[c][a] = i < n ? args.xyz[c * total + o + i] : 0.0;
+            }
+        double E = 0.0, gn = 0.0;
+        int iters = 0, evals = 0, st;
+        if constexpr (MIXED) {
+            const double gtol32 = fmax(args.p.gtol, args.p.gtol_mixed_per_atom * (double)n);
+            const int r32 = lbfgs_run<true>(tm, H, x, g, E, gn, iters, evals, args.p, gtol32,
+                                            args.p.max_iter);
+            if (args.xyz_switch) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int a = 0; a < A; ++a) {
+                        const int i = a * T + threadIdx.x;
+                        if (i < n) args.xyz_switch[c * total + o + i] = x[c][a];
+                    }
+            }
+            if (args.p.polish) {
+                st = lbfgs_run<false>(tm, H, x, g, E, gn, iters, evals, args.p, args.p.gtol,
+                                      args.p.max_iter);
+            } else {
+                E = tm.template eval<false>(x, g);
+                ++evals;
+                double p1[1][A], o1[1];
+#pragma unroll
+                for (int a = 0; a < A; ++a) p1[0][a] = fma(g[2][a], g[2][a], fma(g[1][a], g[1][a], g[0][a] * g[0][a]));
+                team_sum<W, A, 1, Team<W, A>::NVMAX>(p1, o1, *tm.sc, tm.bank);
+                gn = sqrt(o1[0]);
+                if (!isfinite(E) || !isfinite(o1[0]))
+                    st = LJ_NONFINITE;
+                else if (gn < args.p.gtol)
+                    st = LJ_CONVERGED;
+                else if (r32 == LJ_CONVERGED || r32 == kStall)
+                    st = LJ_SWITCHED;
+                else
+                    st = r32 == LJ_NONFINITE ? LJ_LSFAIL : r32;
+            }
+        } else {
+            st = lbfgs_run<false>(tm, H, x, g, E, gn, iters, evals, args.p, args.p.gtol,
+                                  args.p.max_iter);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                const int i = a * T + threadIdx.x;
+                if (i < n) args.xyz[c * total + o + i] = x[c][a];
+            }
+        if (threadIdx.x == 0) {
+            args.energy[b] = E;
+            args.gnorm[b] = gn;
+            args.iters[b] = iters;
+            args.evals[b] = evals;
+            args.status[b] = st;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plan: list the (active) clusters by N descending and split the list into
+// size classes.  One workgroup; rejects clusters whose N is outside
+// [0, max_n] with a per-cluster status instead of running them.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void plan_kernel(const int32_t* offset, int num, int max_n,
+                                                    const int32_t* active, Plan plan,
+                                                    int32_t* status) {
+    __shared__ int cnt[LJ_MAX_ATOMS_MIN + 1];
+    const int t = threadIdx.x;
+    for (int k = t; k <= LJ_MAX_ATOMS_MIN; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    for (int b = t; b < num; b += blockDim.x) {
+        if (active && !active[b]) continue;
+        const int n = offset[b + 1] - offset[b];
+        if (n < 0 || n > max_n) {
+            if (status) status[b] = kStatusBadSize;
+            continue;
+        }
+        atomicAdd(&cnt[n], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = LJ_MAX_ATOMS_MIN; k >= 0; --k) {
+            const int c = cnt[k];
+            cnt[k] = run;
+            run += c;
+        }
+        // classes: (256, 1024], (128, 256], (64, 128], [0, 64]
+        const int s3 = 0, s2 = cnt[256], s1 = cnt[128], s0 = cnt[64];
+        plan.cls[3] = s3;
+        plan.cls[2] = s2;
+        plan.cls[1] = s1;
+        plan.cls[0] = s0;
+        plan.cls[kNumClasses + 3] = s2 - s3;
+        plan.cls[kNumClasses + 2] = s1 - s2;
+        plan.cls[kNumClasses + 1] = s0 - s1;
+        plan.cls[kNumClasses + 0] = run - s0;
+        for (int c = 0; c < kNumClasses; ++c) plan.queue[c] = 0;
+    }
+    __syncthreads();
+    for (int b = t; b < num; b += blockDim.x) {
+        if (active && !active[b]) continue;
+        const int n = offset[b + 1] - offset[b];
+        if (n < 0 || n > max_n) continue;
+        const int pos = atomicAdd(&cnt[n], 1);
+        plan.list[pos] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched energy + gradient: one workgroup per cluster.
+// ---------------------------------------------------------------------------
+template <int MIXED, int W, int A>
+__global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* offset, int64_t total,
+                                                               const double* xyz, double* energy,
+                                                               double* grad) {
+    constexpr int T = kWave * W;
+    __shared__ double4 pos_buf[T * A];
+    __shared__ TeamScratch<W, 3 * A> scratch;
+    const int b = blockIdx.x;
+    const int o = offset[b];
+    const int n = offset[b + 1] - o;
+    if (n < 0 || n > T * A) {  // offsets disagree with the host max_n
+        if (threadIdx.x == 0) energy[b] = __builtin_nan("");
+        return;
+    }
+    Team<W, A> tm;
+    tm.pos64 = pos_buf;
+    tm.pos32 = reinterpret_cast<float4*>(pos_buf);
+    tm.sc = &scratch;
+    tm.bank = 0;
+    tm.n = n;
+    double x[3][A], g[3][A];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int i = a * T + threadIdx.x;
+            x[c][a] = i < n ? xyz[c * total + o + i] : 0.0;
+        }
+    const double E = tm.template eval<MIXED != 0>(x, g);
+    if (threadIdx.x == 0) energy[b] = E;
+    if (grad) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                const int i = a * T + threadIdx.x;
+                if (i < n) grad[c * total + o + i] = g[c][a];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (internal C++ interface used by the C ABI layer).
+// ---------------------------------------------------------------------------
+EvalShape eval_shape(int max_n) {
+    const int n = max_n < 1 ? 1 : max_n;
+    if (n <= 64) return {1, 1};
+    if (n <= 128) return {2, 1};
+    if (n <= 256) return {4, 1};
+    if (n <= 512) return {8, 1};
+    if (n <= 1024) return {16, 1};
+    if (n <= 2048) return {16, 2};
+    return {16, 4};
+}
+
+template <int MIXED>
+static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_t total,
+                                const double* xyz, double* e, double* g, hipStream_t st) {
+    dim3 grid(num), block(kWave * s.W);
+#define LJ_EVAL_CASE(WW, AA)                                                                   \
+    if (s.W == WW && s.A == AA) {                                                              \
+        hipLaunchKernelGGL((energy_grad_kernel<MIXED, WW, AA>), grid, block, 0, st, off, total, \
+                           xyz, e, g);                                                         \
+        return hipGetLastError();                                                              \
+    }
+    LJ_EVAL_CASE(1, 1)
+    LJ_EVAL_CASE(2, 1)
+    LJ_EVAL_CASE(4, 1)
+    LJ_EVAL_CASE(8, 1)
+    LJ_EVAL_CASE(16, 1)
+    LJ_EVAL_CASE(16, 2)
+    LJ_EVAL_CASE(16, 4)
+#undef LJ_EVAL_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_energy_grad(int mixed, int max_n, int num, const int32_t* off, int64_t total,
+                              const double* xyz, double* e, double* g, hipStream_t st) {
+    const EvalShape s = eval_shape(max_n);
+    return mixed ? launch_eval_t<1>(s, num, off, total, xyz, e, g, st)
+                 : launch_eval_t<0>(s, num, off, total, xyz, e, g, st);
+}
+
+// Minimiser class shapes: classes 0-2 keep the history in registers
+// (one, two, four wavefronts); class 3 uses 16 wavefronts and a global ring.
+struct ClassShape {
+    int W, A;
+    bool hreg;
+};
+constexpr ClassShape kClassShape[kNumClasses] = {{1, 1, true}, {2, 1, true}, {4, 1, true},
+                                                 {16, 1, false}};
+
+int class_of(int n) {
+    for (int c = 0; c < kNumClasses; ++c)
+        if (n <= kClassMaxN[c]) return c;
+    return -1;
+}
+
+size_t class_hist_bytes_per_wg(int c) {
+    const ClassShape s = kClassShape[c];
+    return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
+}
+
+template <int MIXED, int W, int A, bool HREG>
+static const void* min_kernel_ptr() {
+    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG>);
+}
+
+const void* minimize_kernel_for(int mixed, int c) {
+    switch (c * 2 + (mixed ? 1 : 0)) {
+        case 0: return min_kernel_ptr<0, 1, 1, true>();
+        case 1: return min_kernel_ptr<1, 1, 1, true>();
+        case 2: return min_kernel_ptr<0, 2, 1, true>();
+        case 3: return min_kernel_ptr<1, 2, 1, true>();
+        case 4: return min_kernel_ptr<0, 4, 1, true>();
+        case 5: return min_kernel_ptr<1, 4, 1, true>();
+        case 6: return min_kernel_ptr<0, 16, 1, false>();
+        case 7: return min_kernel_ptr<1, 16, 1, false>();
+    }
+    return nullptr;
+}
+
+int class_block(int c) { return kWave * kClassShape[c].W; }
+
+hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
+                       int32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, offset, num, max_n, active, plan,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_minimize_class(int mixed, int c, int grid, const MinArgs& a, hipStream_t st) {
+    const void* k = minimize_kernel_for(mixed, c);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {const_cast<MinArgs*>(&a)};
+    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c)), args, 0, st);
+}
+
+}  // namespace lj

@@ -1,0 +1,242 @@
+"""ctypes binding of liblj_bh.so (C ABI in include/lj_bh.h).
+
+Argument marshalling only: torch tensors provide device memory and the
+stream; every step of the method runs in the library's HIP kernels.  The
+library must be built (paper_2510_25938_amd/build.py); importing a function
+without it raises instead of falling back to anything else.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblj_bh.so")
+
+FP64, MIXED = 0, 1
+CONVERGED, MAXITER, LSFAIL, NONFINITE, SWITCHED, BADSIZE = 0, 1, 2, 3, 4, 5
+OK, E_ARG, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4
+MAX_ATOMS_EVAL, MAX_ATOMS_MIN, MAX_M, MAX_CANDS = 4096, 1024, 10, 64
+EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
+            "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_status_string",
+            "lj_last_error", "lj_abi_version"]
+
+
+class Batch(C.Structure):
+    _fields_ = [("num", C.c_int32), ("offset", C.c_void_p), ("max_n", C.c_int32),
+                ("total_atoms", C.c_int64)]
+
+
+class LbfgsParams(C.Structure):
+    _fields_ = [("m", C.c_int32), ("gtol", C.c_double), ("max_iter", C.c_int32),
+                ("max_step", C.c_double), ("c1", C.c_double), ("max_ls", C.c_int32),
+                ("curv_eps", C.c_double), ("gtol_mixed_per_atom", C.c_double),
+                ("polish", C.c_int32), ("ls_noise", C.c_double)]
+
+
+class BhParams(C.Structure):
+    _fields_ = [("cands", C.c_int32), ("kT", C.c_double), ("adapt_interval", C.c_int32),
+                ("target_rate", C.c_double), ("factor", C.c_double), ("seed", C.c_uint64)]
+
+
+class BhState(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("xyz_cur", "e_cur", "step", "win_accepts",
+                                          "step_index", "e_best_seen", "e_best_acc",
+                                          "xyz_best")]
+
+
+class BhTrace(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("e_trial", "accepted", "e_best", "e_best_acc", "e_cur",
+                                          "step", "e_cand")] + [("capacity_steps", C.c_int32)]
+
+
+class LJError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LJError(f"{LIB_PATH} is missing: build it with paper_2510_25938_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.lj_energy_grad_batch.argtypes = [C.POINTER(Batch), vp, vp, vp, i32, vp]
+        L.lj_energy_grad_batch.restype = i32
+        L.lj_lbfgs_defaults.argtypes = [C.POINTER(LbfgsParams)]
+        L.lj_lbfgs_defaults.restype = None
+        L.lj_minimize_workspace_bytes.argtypes = [C.POINTER(Batch), C.POINTER(LbfgsParams), i32]
+        L.lj_minimize_workspace_bytes.restype = C.c_size_t
+        L.lj_bh_minimize_batch.argtypes = [C.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp,
+                                           C.POINTER(LbfgsParams), i32, vp, C.c_size_t, vp]
+        L.lj_bh_minimize_batch.restype = i32
+        L.lj_bh_workspace_bytes.argtypes = [C.POINTER(Batch), C.POINTER(BhParams),
+                                            C.POINTER(LbfgsParams), i32]
+        L.lj_bh_workspace_bytes.restype = C.c_size_t
+        L.lj_bh_step.argtypes = [C.POINTER(Batch), C.POINTER(BhState), C.POINTER(BhParams),
+                                 C.POINTER(LbfgsParams), i32, i32, C.POINTER(BhTrace), vp,
+                                 C.c_size_t, vp]
+        L.lj_bh_step.restype = i32
+        L.lj_status_string.argtypes = [i32]
+        L.lj_status_string.restype = C.c_char_p
+        L.lj_last_error.argtypes = []
+        L.lj_last_error.restype = C.c_char_p
+        L.lj_abi_version.argtypes = []
+        L.lj_abi_version.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        L = lib()
+        raise LJError(f"{L.lj_status_string(status).decode()}: {L.lj_last_error().decode()}",
+                      status)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def precision_code(p):
+    if isinstance(p, int):
+        return p
+    return {"fp64": FP64, "mixed": MIXED}[p]
+
+
+def lbfgs_params(**kw):
+    p = LbfgsParams()
+    lib().lj_lbfgs_defaults(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class ClusterBatch:
+    """A ragged batch: host sizes plus the device int32 prefix-sum offsets."""
+
+    def __init__(self, offset, device="cuda"):
+        off = np.asarray(offset, dtype=np.int64)
+        if off.ndim != 1 or off.size < 1 or off[0] != 0 or np.any(np.diff(off) < 0):
+            raise ValueError("offset must be nondecreasing prefix sums starting at 0")
+        self.sizes = np.diff(off)
+        self.num = int(self.sizes.size)
+        self.total = int(off[-1])
+        self.max_n = int(self.sizes.max()) if self.num else 0
+        self.offset_host = off.astype(np.int32)
+        self.offset = torch.from_numpy(self.offset_host).to(device)
+
+    def desc(self, max_n=None):
+        return Batch(self.num, self.offset.data_ptr(), self.max_n if max_n is None else max_n,
+                     self.total)
+
+
+def energy_grad(batch, xyz, precision="fp64", grad=True, stream=None):
+    """Eq. (1) energies [num] and gradient planes [3][total] (None if grad=False)."""
+    assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
+    E = torch.empty(batch.num, dtype=torch.float64, device=xyz.device)
+    g = torch.empty_like(xyz) if grad else None
+    _check(lib().lj_energy_grad_batch(C.byref(batch.desc()), _ptr(xyz), _ptr(E), _ptr(g),
+                                      precision_code(precision), _stream(stream)))
+    return E, g
+
+
+def minimize_workspace_bytes(batch, params=None, precision="fp64"):
+    params = params or lbfgs_params()
+    return int(lib().lj_minimize_workspace_bytes(C.byref(batch.desc()), C.byref(params),
+                                                 precision_code(precision)))
+
+
+def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, workspace=None,
+             stream=None, inplace=False):
+    """Local minimisation of every cluster; returns a dict of device tensors."""
+    params = params or lbfgs_params()
+    assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
+    dev = xyz.device
+    x = xyz if inplace else xyz.clone()
+    out = dict(xyz=x, energy=torch.empty(batch.num, dtype=torch.float64, device=dev),
+               gnorm=torch.empty(batch.num, dtype=torch.float64, device=dev),
+               iters=torch.empty(batch.num, dtype=torch.int32, device=dev),
+               evals=torch.empty(batch.num, dtype=torch.int32, device=dev),
+               status=torch.empty(batch.num, dtype=torch.int32, device=dev))
+    out["xyz_switch"] = torch.zeros_like(x) if switch_point else None
+    if workspace is None:
+        nb = minimize_workspace_bytes(batch, params, precision)
+        if nb == 0 and batch.num > 0:
+            _check(E_ARG)
+        workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _check(lib().lj_bh_minimize_batch(C.byref(batch.desc()), _ptr(x), _ptr(out["energy"]),
+                                      _ptr(out["gnorm"]), _ptr(out["iters"]), _ptr(out["evals"]),
+                                      _ptr(out["status"]), _ptr(out["xyz_switch"]),
+                                      C.byref(params), precision_code(precision),
+                                      _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def bh_params(cands=8, kT=0.8, adapt_interval=10, target_rate=0.5, factor=0.9, seed=0):
+    return BhParams(cands, kT, adapt_interval, target_rate, factor, seed)
+
+
+class BasinHopping:
+    """Device state of many independent basin-hopping chains.
+
+    `xyz_min` / `e_min` must be local minima (e.g. from `minimize`); the
+    chains start there with step size `step0`.
+    """
+
+    def __init__(self, batch, xyz_min, e_min, bh, params=None, precision="fp64", step0=0.4,
+                 trace_steps=0, trace_candidates=False):
+        self.batch, self.bh = batch, bh
+        self.params = params or lbfgs_params()
+        self.precision = precision_code(precision)
+        dev = xyz_min.device
+        C_ = batch.num
+        self.xyz_cur = xyz_min.clone()
+        self.xyz_best = xyz_min.clone()
+        self.e_cur = e_min.clone().to(torch.float64)
+        self.e_best_acc = self.e_cur.clone()
+        self.e_best_seen = torch.full((C_,), float("inf"), dtype=torch.float64, device=dev)
+        self.step_size = torch.full((C_,), float(step0), dtype=torch.float64, device=dev)
+        self.win_accepts = torch.zeros(C_, dtype=torch.int32, device=dev)
+        self.step_index = torch.zeros(C_, dtype=torch.int64, device=dev)
+        self.state = BhState(*[t.data_ptr() for t in (self.xyz_cur, self.e_cur, self.step_size,
+                                                      self.win_accepts, self.step_index,
+                                                      self.e_best_seen, self.e_best_acc,
+                                                      self.xyz_best)])
+        self.trace = None
+        self._trace_desc = None
+        if trace_steps > 0:
+            f = dict(dtype=torch.float64, device=dev)
+            self.trace = dict(e_trial=torch.full((C_, trace_steps), float("nan"), **f),
+                              accepted=torch.zeros((C_, trace_steps), dtype=torch.int8, device=dev),
+                              e_best=torch.full((C_, trace_steps), float("nan"), **f),
+                              e_best_acc=torch.full((C_, trace_steps), float("nan"), **f),
+                              e_cur=torch.full((C_, trace_steps), float("nan"), **f),
+                              step=torch.full((C_, trace_steps), float("nan"), **f))
+            self.trace["e_cand"] = (torch.full((C_, trace_steps, bh.cands), float("nan"), **f)
+                                    if trace_candidates else None)
+            self._trace_desc = BhTrace(*[None if self.trace[k] is None else self.trace[k].data_ptr()
+                                         for k in ("e_trial", "accepted", "e_best", "e_best_acc",
+                                                   "e_cur", "step", "e_cand")], trace_steps)
+        nb = int(lib().lj_bh_workspace_bytes(C.byref(batch.desc()), C.byref(bh),
+                                             C.byref(self.params), self.precision))
+        if nb == 0:
+            _check(E_ARG)
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def step(self, num_steps=1, stream=None):
+        tr = C.byref(self._trace_desc) if self._trace_desc is not None else None
+        _check(lib().lj_bh_step(C.byref(self.batch.desc()), C.byref(self.state), C.byref(self.bh),
+                                C.byref(self.params), self.precision, int(num_steps), tr,
+                                _ptr(self.workspace), self.workspace.numel(), _stream(stream)))

@@ -1,0 +1,89 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol declared in
+include/lj_bh.h, and rejects bad arguments on the host before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2510_25938_amd import lj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lj_bh.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lj_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(lj.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lj.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version():
+    L = lj.lib()
+    assert L.lj_abi_version() == 1
+    assert L.lj_status_string(lj.OK) == b"LJ_OK"
+    for s in (lj.E_ARG, lj.E_HIP, lj.E_WORKSPACE, lj.E_UNSUPPORTED):
+        assert L.lj_status_string(s).startswith(b"LJ_E_")
+
+
+def test_defaults():
+    p = lj.lbfgs_params()
+    assert (p.m, p.gtol, p.max_iter, p.max_step, p.c1, p.max_ls) == (10, 1e-6, 10000, 0.2, 1e-4, 30)
+    assert p.polish == 1 and p.curv_eps == 1e-10
+
+
+def test_argument_errors_are_host_side():
+    L = lj.lib()
+    bad = lj.Batch(-1, None, 0, 0)
+    assert L.lj_energy_grad_batch(C.byref(bad), None, None, None, lj.FP64, None) == lj.E_ARG
+    assert b"num" in L.lj_last_error()
+    big = lj.Batch(1, 16, lj.MAX_ATOMS_EVAL + 1, 10)
+    assert L.lj_energy_grad_batch(C.byref(big), None, None, None, lj.FP64, None) == lj.E_UNSUPPORTED
+    big = lj.Batch(1, 16, lj.MAX_ATOMS_MIN + 1, 10)
+    p = lj.lbfgs_params()
+    assert (L.lj_bh_minimize_batch(C.byref(big), None, None, None, None, None, None, None,
+                                   C.byref(p), lj.FP64, None, 0, None) == lj.E_UNSUPPORTED)
+    ok = lj.Batch(2, 16, 13, 26)
+    assert L.lj_energy_grad_batch(C.byref(ok), 16, 16, None, 7, None) == lj.E_ARG
+    p.m = 11
+    assert (L.lj_bh_minimize_batch(C.byref(ok), None, None, None, None, None, None, None,
+                                   C.byref(p), lj.FP64, None, 0, None) == lj.E_ARG)
+    p = lj.lbfgs_params(gtol=0.0)
+    assert (L.lj_bh_minimize_batch(C.byref(ok), None, None, None, None, None, None, None,
+                                   C.byref(p), lj.FP64, None, 0, None) == lj.E_ARG)
+    inconsistent = lj.Batch(2, 16, 13, 27)  # total_atoms > num * max_n
+    assert L.lj_energy_grad_batch(C.byref(inconsistent), 16, 16, None, 0, None) == lj.E_ARG
+    bh = lj.bh_params(cands=lj.MAX_CANDS + 1)
+    p = lj.lbfgs_params()
+    assert L.lj_bh_workspace_bytes(C.byref(ok), C.byref(bh), C.byref(p), lj.FP64) == 0
+    st = lj.BhState()
+    bh = lj.bh_params()
+    assert (L.lj_bh_step(C.byref(ok), C.byref(st), C.byref(bh), C.byref(p), lj.FP64, 1, None,
+                         None, 0, None) == lj.E_ARG)  # NULL state arrays
+
+
+def test_empty_batches_are_no_ops():
+    L = lj.lib()
+    empty = lj.Batch(0, None, 0, 0)
+    p = lj.lbfgs_params()
+    assert L.lj_energy_grad_batch(C.byref(empty), None, None, None, lj.FP64, None) == lj.OK
+    assert (L.lj_bh_minimize_batch(C.byref(empty), None, None, None, None, None, None, None,
+                                   C.byref(p), lj.MIXED, None, 0, None) == lj.OK)
+
+
+def test_cluster_batch_validation():
+    with pytest.raises(ValueError):
+        lj.ClusterBatch([1, 2], device="cpu")
+    with pytest.raises(ValueError):
+        lj.ClusterBatch([0, 5, 3], device="cpu")
+    b = lj.ClusterBatch([0, 13, 13, 51], device="cpu")
+    assert b.num == 3 and b.max_n == 38 and b.total == 51 and list(b.sizes) == [13, 0, 38]
