@@ -281,9 +281,12 @@ int lj_o_two_loop(int n, int hist, const double* S, const double* Y, const doubl
  * -g if d is not a descent direction; cap the largest per-atom displacement
  * of d at max_step; backtrack alpha = 1, 1/2, 1/4, ... until the Armijo
  * condition E(x + alpha d) <= E + c1 alpha g.d holds; form s and y and store
- * them when the curvature s.y is positive enough.  A failed line search with
- * stored pairs discards the pairs and retries from -g (not counted as an
- * iteration); a failed line search from -g ends the run (LSFAIL).
+ * them when the curvature s.y is positive enough.  A line search fails when
+ * no trial passes, or when the accepted trial point equals x (s = 0: the
+ * Armijo test cannot see a decrease below half an ulp of E, and a null step
+ * makes no progress).  A failed line search with stored pairs discards the
+ * pairs and retries from -g (not counted as an iteration); a failed line
+ * search from -g ends the run (LSFAIL).
  */
 static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, double* gnorm_out,
                         int32_t* iters_out, int32_t* evals_out) {
@@ -382,6 +385,17 @@ static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, doub
         double sy = dot3(n, d, q, tmp);
         double yy = dot3(n, q, q, tmp);
         double ss = dot3(n, d, d, tmp);
+        if (ss == 0.0) {
+            /* The accepted trial point equals x in every coordinate (alpha d is
+             * below the coordinates' resolution): no progress is possible along
+             * d, so this counts as a failed line search. */
+            if (hist > 0) {
+                hist = 0;
+                continue;
+            }
+            status = LJ_O_LSFAIL;
+            break;
+        }
         if (m > 0 && sy > p->curv_eps * sqrt(ss * yy)) {
             newest = (newest + 1) % m;
             vec_copy(n, S[newest], d);

@@ -27,21 +27,50 @@ __device__ __forceinline__ double uniform(double v) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
-// Sum over the 64 lanes by an xor butterfly.  Step k adds the value of the
-// lane 2^k away, so after six steps every lane holds the balanced binary tree
-// sum over the lane index (IEEE addition is commutative, so the two lanes of
-// each pair compute identical bits).
+// Sum over the 64 lanes in balanced-tree order.  Levels 1-4 run inside each
+// 16-lane row with DPP lane permutes: quad_perm [1,0,3,2] and [2,3,0,1] pair
+// lanes 2^0 and 2^1 apart; once every quad holds one value, row_half_mirror
+// pairs each quad with the other quad of its 8-lane half, and once every
+// half holds one value, row_mirror pairs the two halves of the row.  Each
+// level adds the partner's value (IEEE addition is commutative, so both
+// lanes of a pair hold identical bits).  The four row sums r0..r3 are then
+// read out and combined as (r0 + r1) + (r2 + r3).  The result equals the
+// pairwise sum over the lane index and is wave-uniform.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, CTRL, 0xF, 0xF, false);
+    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, CTRL, 0xF, 0xF, false);
+    return *reinterpret_cast<double*>(&b);
+}
+
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    b.x = __builtin_amdgcn_readlane(b.x, lane);
+    b.y = __builtin_amdgcn_readlane(b.y, lane);
+    return *reinterpret_cast<double*>(&b);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) v = v + __shfl_xor(v, m, kWave);
-    return v;
+    v = v + dpp<kDppXor1>(v);
+    v = v + dpp<kDppXor2>(v);
+    v = v + dpp<kDppHalfMirror>(v);
+    v = v + dpp<kDppMirror>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) v = fmax(v, __shfl_xor(v, m, kWave));
-    return v;
+    v = fmax(v, dpp<kDppXor1>(v));
+    v = fmax(v, dpp<kDppXor2>(v));
+    v = fmax(v, dpp<kDppHalfMirror>(v));
+    v = fmax(v, dpp<kDppMirror>(v));
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Balanced tree over K values (K a power of two): ((r0+r1)+(r2+r3))+...
@@ -81,7 +110,7 @@ __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV
         for (int k = 0; k < NV; ++k) {
             double r[A];
 #pragma unroll
-            for (int a = 0; a < A; ++a) r[a] = uniform(ws[k][a]);
+            for (int a = 0; a < A; ++a) r[a] = ws[k][a];
             out[k] = tree<A>(r);
         }
     } else {
@@ -118,7 +147,7 @@ __device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<
     for (int a = 1; a < A; ++a) m = fmax(m, vals[a]);
     m = wave_max(m);
     if constexpr (W == 1) {
-        return uniform(m);
+        return m;
     } else {
         const int w = threadIdx.x / kWave;
         if (threadIdx.x % kWave == 0) sc.v[bank][0][w] = m;
@@ -157,15 +186,14 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
             const double dy = x[1][a] - pj.y;
             const double dz = x[2][a] - pj.z;
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double q = 1.0 / r2;
+            // the self pair (r2 = 0) gets q = 0, so it adds exactly zero
+            const double q = (j == a * T + t) ? 0.0 : 1.0 / r2;
             const double s6 = (q * q) * q;
-            const double te = fma(s6, s6, -s6);
+            e[a] = e[a] + fma(s6, s6, -s6);
             const double f = (q * s6) * fma(-48.0, s6, 24.0);
-            const bool self = (j == a * T + t);
-            e[a] = self ? e[a] : e[a] + te;
-            g[0][a] = self ? g[0][a] : fma(f, dx, g[0][a]);
-            g[1][a] = self ? g[1][a] : fma(f, dy, g[1][a]);
-            g[2][a] = self ? g[2][a] : fma(f, dz, g[2][a]);
+            g[0][a] = fma(f, dx, g[0][a]);
+            g[1][a] = fma(f, dy, g[1][a]);
+            g[2][a] = fma(f, dz, g[2][a]);
         }
     }
 }
@@ -199,15 +227,13 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
                 const float dy = xf[1][a] - pj.y;
                 const float dz = xf[2][a] - pj.z;
                 const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const float q = __builtin_amdgcn_rcpf(r2);
+                const float q = (j == a * T + t) ? 0.0f : __builtin_amdgcn_rcpf(r2);
                 const float s6 = (q * q) * q;
-                const float ee = fmaf(s6, s6, -s6);
+                te[a] = te[a] + fmaf(s6, s6, -s6);
                 const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
-                const bool self = (j == a * T + t);
-                te[a] = self ? te[a] : te[a] + ee;
-                tg[0][a] = self ? tg[0][a] : fmaf(f, dx, tg[0][a]);
-                tg[1][a] = self ? tg[1][a] : fmaf(f, dy, tg[1][a]);
-                tg[2][a] = self ? tg[2][a] : fmaf(f, dz, tg[2][a]);
+                tg[0][a] = fmaf(f, dx, tg[0][a]);
+                tg[1][a] = fmaf(f, dy, tg[1][a]);
+                tg[2][a] = fmaf(f, dz, tg[2][a]);
             }
         }
 #pragma unroll

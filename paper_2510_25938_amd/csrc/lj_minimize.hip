@@ -23,7 +23,7 @@ namespace lj {
 template <int W, int A>
 struct Team {
     static constexpr int T = kWave * W;
-    static constexpr int NVMAX = 3 * A;
+    static constexpr int NVMAX = 4 * A;
     double4* pos64;
     float4* pos32;
     TeamScratch<W, NVMAX>* sc;
@@ -40,20 +40,23 @@ struct Team {
         return o[0];
     }
 
-    // (u.v, v.v, u.u) in one reduction.
-    __device__ __forceinline__ void dot3(const double (&u)[3][A], const double (&v)[3][A], double& uv,
-                                         double& vv, double& uu) {
-        double p[3][A], o[3];
+    // (s.y, y.y, s.s, w.w) in one reduction.
+    __device__ __forceinline__ void dot4(const double (&s)[3][A], const double (&y)[3][A],
+                                         const double (&w)[3][A], double& sy, double& yy,
+                                         double& ss, double& ww) {
+        double p[4][A], o[4];
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-            p[0][a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
-            p[1][a] = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
-            p[2][a] = fma(u[2][a], u[2][a], fma(u[1][a], u[1][a], u[0][a] * u[0][a]));
+            p[0][a] = fma(s[2][a], y[2][a], fma(s[1][a], y[1][a], s[0][a] * y[0][a]));
+            p[1][a] = fma(y[2][a], y[2][a], fma(y[1][a], y[1][a], y[0][a] * y[0][a]));
+            p[2][a] = fma(s[2][a], s[2][a], fma(s[1][a], s[1][a], s[0][a] * s[0][a]));
+            p[3][a] = fma(w[2][a], w[2][a], fma(w[1][a], w[1][a], w[0][a] * w[0][a]));
         }
-        team_sum<W, A, 3, NVMAX>(p, o, *sc, bank);
-        uv = o[0];
-        vv = o[1];
-        uu = o[2];
+        team_sum<W, A, 4, NVMAX>(p, o, *sc, bank);
+        sy = o[0];
+        yy = o[1];
+        ss = o[2];
+        ww = o[3];
     }
 
     // Largest per-atom squared norm of v.
@@ -275,18 +278,11 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
     H.clear();
     E = tm.template eval<F32>(x, g);
     ++evals;
+    double gg = tm.dot(g, g);  // later iterations get it from the curvature reduction
     int it = 0;
     int stall = 0;
     const double ms2 = p.max_step * p.max_step;
     for (;;) {
-        double gg;
-        {
-            double p1[1][A], o[1];
-#pragma unroll
-            for (int a = 0; a < A; ++a) p1[0][a] = fma(g[2][a], g[2][a], fma(g[1][a], g[1][a], g[0][a] * g[0][a]));
-            team_sum<W, A, 1, Team<W, A>::NVMAX>(p1, o, *tm.sc, tm.bank);
-            gg = o[0];
-        }
         gnorm = sqrt(gg);
         if (!isfinite(E) || !isfinite(gg)) {
             iters += it;
@@ -362,8 +358,23 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
                 d[c][a] = xt[c][a] - x[c][a];
                 g[c][a] = gt[c][a] - g[c][a];
             }
-        double sy, yy, ss;
-        tm.dot3(d, g, sy, yy, ss);
+        double sy, yy, ss, ggt;
+        tm.dot4(d, g, gt, sy, yy, ss, ggt);
+        if (ss == 0.0) {
+            // Null step: the accepted trial point equals x, so no progress is
+            // possible along d; treated as a failed line search.  g holds y
+            // here; x_t == x implies g_t == g, so restore g from g_t.
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < A; ++a) g[c][a] = gt[c][a];
+            if (uniform(H.hist) > 0) {
+                H.clear();
+                continue;
+            }
+            iters += it;
+            return LJ_LSFAIL;
+        }
         if (p.m > 0 && sy > p.curv_eps * sqrt(ss * yy)) H.push(d, g, 1.0 / sy, sy / yy, p.m);
         if constexpr (F32) stall = (Et < E) ? 0 : stall + 1;
 #pragma unroll
@@ -374,6 +385,7 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
                 g[c][a] = gt[c][a];
             }
         E = Et;
+        gg = ggt;
         ++it;
         if constexpr (F32) {
             if (stall >= 5) {
@@ -391,7 +403,7 @@ template <int MIXED, int W, int A, bool HREG>
 __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
-    __shared__ TeamScratch<W, 3 * A> scratch;
+    __shared__ TeamScratch<W, 4 * A> scratch;
     __shared__ int claim;
 
     Team<W, A> tm;
@@ -446,12 +458,9 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
             } else {
                 E = tm.template eval<false>(x, g);
                 ++evals;
-                double p1[1][A], o1[1];
-#pragma unroll
-                for (int a = 0; a < A; ++a) p1[0][a] = fma(g[2][a], g[2][a], fma(g[1][a], g[1][a], g[0][a] * g[0][a]));
-                team_sum<W, A, 1, Team<W, A>::NVMAX>(p1, o1, *tm.sc, tm.bank);
-                gn = sqrt(o1[0]);
-                if (!isfinite(E) || !isfinite(o1[0]))
+                const double gg = tm.dot(g, g);
+                gn = sqrt(gg);
+                if (!isfinite(E) || !isfinite(gg))
                     st = LJ_NONFINITE;
                 else if (gn < args.p.gtol)
                     st = LJ_CONVERGED;
@@ -541,7 +550,7 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
                                                                double* grad) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
-    __shared__ TeamScratch<W, 3 * A> scratch;
+    __shared__ TeamScratch<W, 4 * A> scratch;
     const int b = blockIdx.x;
     const int o = offset[b];
     const int n = offset[b + 1] - o;

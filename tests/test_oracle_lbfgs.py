@@ -183,3 +183,29 @@ def test_scipy_lbfgsb_same_minimum(n, seed):
     off, x = one(x0)
     r = O.minimize(off, x)
     assert r["energy"][0] == pytest.approx(res.fun, rel=1e-9)
+
+
+def test_null_step_is_a_failed_line_search():
+    """A start with two atoms 0.01 apart: the first capped step stores a pair
+    with an enormous y, so the next direction is below the coordinates'
+    resolution (x + d == x).  Such a null step must count as a failed line
+    search (history cleared, restart from -g), not as an accepted step, or the
+    run would stall at E ~ 1e6 until the iteration cap."""
+    from paper_2510_25938_amd.inputs import lj38_batch
+    off, x = lj38_batch().starts()
+    b = 559  # this workload's start with the closest pair (r = 0.01)
+    xb = np.ascontiguousarray(x[:, off[b]:off[b + 1]])
+    o1 = np.array([0, 38], np.int32)
+    D = np.linalg.norm(xb[:, :, None] - xb[:, None, :], axis=0) + 9 * np.eye(38)
+    assert D.min() < 0.02
+    r = O.minimize(o1, xb)
+    assert r["status"][0] in (O.CONVERGED, O.LSFAIL)
+    assert r["iters"][0] < 2000 and r["energy"][0] < -150.0
+
+
+def test_lj38_workload_has_no_iteration_cap_stragglers():
+    from paper_2510_25938_amd.inputs import lj38_batch
+    off, x = lj38_batch(256).starts()
+    r = O.minimize(off, x)
+    assert np.all(r["status"] != O.MAXITER) and r["iters"].max() < 2000
+    assert np.mean(r["status"] == O.CONVERGED) > 0.97
