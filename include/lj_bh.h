@@ -215,6 +215,38 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
                      const lj_lbfgs_params* params, int32_t precision, int32_t num_steps,
                      const lj_bh_trace* trace, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Launch-schedule table (process-wide).  The library picks a workgroup shape
+ * per call from this table, falling back to a built-in rule:
+ *   LJ_SCHED_EVAL      lj_energy_grad_batch: W wavefronts per workgroup (1, 2,
+ *                      4, 8, 16) x A atom slots per lane (1, 2, 4), keyed by
+ *                      precision and max_n rounded up to a power of two;
+ *                      64*W*A must be >= max_n.
+ *   LJ_SCHED_MIN_LARGE minimiser shape for clusters of 257..1024 atoms, keyed by
+ *                      precision: w = 0 (16 wavefronts x 1 atom), 1 (8 x 2) or
+ *                      2 (4 x 4); a is ignored.
+ * Results never depend on the schedule in LJ_FP64 (fixed summation order).
+ */
+#define LJ_SCHED_EVAL 0
+#define LJ_SCHED_MIN_LARGE 1
+lj_status lj_set_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t w, int32_t a);
+lj_status lj_get_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t* w, int32_t* a);
+
+/*
+ * lj_autotune - time every candidate schedule for this batch shape and record
+ * the fastest in the schedule table: all lj_energy_grad_batch shapes holding
+ * max_n atoms (at most twice the padded size), and for max_n in 257..1024 the
+ * three large-cluster minimiser shapes (timed on a 3-iteration minimisation of
+ * a copy of xyz).  xyz [3][total_atoms] is read only.  Unlike every other
+ * call this one SYNCHRONISES the stream (it times launches with HIP events).
+ *   ws, ws_bytes     scratch of at least lj_autotune_workspace_bytes().
+ *   best_eval_ms     fastest pair-kernel time (nullable).
+ *   best_min_ms      fastest minimiser time, -1 if not tuned (nullable).
+ */
+size_t lj_autotune_workspace_bytes(const lj_batch* batch, int32_t precision);
+lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precision, void* ws,
+                      size_t ws_bytes, void* stream, float* best_eval_ms, float* best_min_ms);
+
 /* Static description of a status code. */
 const char* lj_status_string(lj_status s);
 

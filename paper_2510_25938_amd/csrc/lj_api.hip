@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -106,17 +107,43 @@ lj::LbfgsDev to_dev(const lj_lbfgs_params* p) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Launch-schedule table, filled by lj_autotune / lj_set_schedule.  Keys:
+// eval: (precision, next_pow2(max_n)); large minimiser: (precision).
+std::mutex g_sched_mu;
+std::map<std::pair<int, int>, lj::EvalShape> g_eval_sched;
+int g_large_sched[2] = {0, 0};
+
+int pow2_at_least(int n) {
+    int p = 1;
+    while (p < n) p *= 2;
+    return p;
+}
+
+lj::EvalShape eval_schedule(int precision, int max_n) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    auto it = g_eval_sched.find({precision, pow2_at_least(max_n < 1 ? 1 : max_n)});
+    if (it != g_eval_sched.end() && it->second.W * 64 * it->second.A >= max_n) return it->second;
+    return lj::eval_shape(max_n);
+}
+
+int large_schedule(int precision) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    return g_large_sched[precision == LJ_MIXED ? 1 : 0];
+}
+
 // Workspace carve-up of one minimisation call.
 struct MinLayout {
     size_t list = 0, cls = 0, queue = 0, hist = 0, total = 0;
     int top_class = -1;
+    int large = 0;
     int grid[lj::kNumClasses] = {0, 0, 0, 0};
 };
 
-lj_status min_layout(int num, int max_n, int mixed, MinLayout& L) {
+lj_status min_layout(int num, int max_n, int mixed, MinLayout& L, int large = -1) {
     DeviceInfo di;
     lj_status s = device_info(di);
     if (s != LJ_OK) return s;
+    L.large = large >= 0 ? large : large_schedule(mixed ? LJ_MIXED : LJ_FP64);
     size_t off = 0;
     L.list = off;
     off = align_up(off + sizeof(int32_t) * (size_t)(num > 0 ? num : 1));
@@ -125,18 +152,33 @@ lj_status min_layout(int num, int max_n, int mixed, MinLayout& L) {
     L.queue = off;
     off = align_up(off + sizeof(int32_t) * lj::kNumClasses);
     L.top_class = lj::class_of(max_n < 0 ? 0 : max_n);
-    for (int c = 0; c <= L.top_class; ++c) {
+    auto grid_for = [&](int c, int large_shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, lj::minimize_kernel_for(mixed, c), lj::class_block(c), 0));
+            &per_cu, lj::minimize_kernel_for(mixed, c, large_shape),
+            lj::class_block(c, large_shape), 0));
         if (per_cu < 1) per_cu = 1;
         long g = (long)per_cu * di.cus;
         if (g > num) g = num;
         if (g < 1) g = 1;
-        L.grid[c] = (int)g;
-    }
+        g_out = (int)g;
+        return LJ_OK;
+    };
+    for (int c = 0; c <= L.top_class; ++c)
+        if ((s = grid_for(c, L.large, L.grid[c])) != LJ_OK) return s;
     L.hist = off;
-    if (L.top_class >= 3) off = align_up(off + lj::class_hist_bytes_per_wg(3) * (size_t)L.grid[3]);
+    if (L.top_class >= 3) {
+        // sized for the largest grid of any large-cluster shape, so a workspace
+        // stays valid whichever shape the schedule table selects
+        size_t hist = 0;
+        for (int k = 0; k < lj::kNumLargeShapes; ++k) {
+            int g = 0;
+            if ((s = grid_for(3, k, g)) != LJ_OK) return s;
+            const size_t b = lj::class_hist_bytes_per_wg(3, k) * (size_t)g;
+            if (b > hist) hist = b;
+        }
+        off = align_up(off + hist);
+    }
     L.total = off;
     return LJ_OK;
 }
@@ -166,7 +208,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     for (int c = L.top_class; c >= 0; --c) {  // largest clusters first
         a.cls = c;
         a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.grid[c], a, st));
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.grid[c], a, st));
     }
     return LJ_OK;
 }
@@ -284,6 +326,7 @@ void key_add(std::vector<unsigned char>& k, const T& v) {
     k.insert(k.end(), p, p + sizeof(T));
 }
 
+
 }  // namespace
 
 extern "C" {
@@ -330,9 +373,9 @@ lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double*
     DeviceInfo di;
     s = device_info(di);
     if (s != LJ_OK) return s;
-    LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, batch->max_n, batch->num,
-                                      batch->offset, batch->total_atoms, xyz, energy, grad,
-                                      static_cast<hipStream_t>(stream)));
+    LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, eval_schedule(precision, batch->max_n),
+                                      batch->num, batch->offset, batch->total_atoms, xyz, energy,
+                                      grad, static_cast<hipStream_t>(stream)));
     return LJ_OK;
 }
 
@@ -443,22 +486,184 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
         hipGraph_t graph = nullptr;
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (s != LJ_OK) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             return s;
         }
         if (ec != hipSuccess) return fail(LJ_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
         ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         if (ec != hipSuccess) return fail(LJ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ec));
         std::lock_guard<std::mutex> lk(g_graph_mu);
         if (g_graphs.size() >= kMaxGraphs) {
-            hipGraphExecDestroy(g_graphs.front().exec);
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
             g_graphs.erase(g_graphs.begin());
         }
         g_graphs.push_back(GraphEntry{key, dev, exec});
     }
     for (int k = 0; k < num_steps; ++k) LJ_HIP_TRY(hipGraphLaunch(exec, st));
     return LJ_OK;
+}
+
+lj_status lj_set_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t w, int32_t a) {
+    g_err.clear();
+    if (precision != LJ_FP64 && precision != LJ_MIXED) return fail(LJ_E_ARG, "bad precision");
+    if (kind == LJ_SCHED_EVAL) {
+        lj::EvalShape sh{w, a};
+        if (!lj::eval_shape_supported(sh)) return fail(LJ_E_ARG, "unsupported shape %dx%d", w, a);
+        if (max_n < 0 || max_n > LJ_MAX_ATOMS_EVAL) return fail(LJ_E_ARG, "max_n out of range");
+        if (64 * w * a < max_n) return fail(LJ_E_ARG, "shape %dx%d holds fewer than %d atoms", w, a, max_n);
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_eval_sched[{precision, pow2_at_least(max_n < 1 ? 1 : max_n)}] = sh;
+        return LJ_OK;
+    }
+    if (kind == LJ_SCHED_MIN_LARGE) {
+        if (w < 0 || w >= lj::kNumLargeShapes) return fail(LJ_E_ARG, "large-cluster shape %d", w);
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_large_sched[precision == LJ_MIXED ? 1 : 0] = w;
+        return LJ_OK;
+    }
+    return fail(LJ_E_ARG, "unknown schedule kind %d", kind);
+}
+
+lj_status lj_get_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t* w, int32_t* a) {
+    g_err.clear();
+    if (!w || !a) return fail(LJ_E_ARG, "NULL output");
+    if (precision != LJ_FP64 && precision != LJ_MIXED) return fail(LJ_E_ARG, "bad precision");
+    if (kind == LJ_SCHED_EVAL) {
+        const lj::EvalShape sh = eval_schedule(precision, max_n);
+        *w = sh.W;
+        *a = sh.A;
+        return LJ_OK;
+    }
+    if (kind == LJ_SCHED_MIN_LARGE) {
+        *w = large_schedule(precision);
+        *a = 0;
+        return LJ_OK;
+    }
+    return fail(LJ_E_ARG, "unknown schedule kind %d", kind);
+}
+
+size_t lj_autotune_workspace_bytes(const lj_batch* batch, int32_t precision) {
+    if (check_batch(batch, LJ_MAX_ATOMS_EVAL, "lj_autotune_workspace_bytes") != LJ_OK) return 0;
+    size_t off = align_up(sizeof(double) * (size_t)(batch->num > 0 ? batch->num : 1));  // energy
+    off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);              // grad
+    if (batch->max_n > 256 && batch->max_n <= LJ_MAX_ATOMS_MIN) {
+        off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);  // xyz copy
+        off = align_up(off + 5 * sizeof(double) * (size_t)batch->num);          // outputs
+        MinLayout L;
+        if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L) != LJ_OK) return 0;
+        off = align_up(off + L.total);
+    }
+    return off;
+}
+
+lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precision, void* ws,
+                      size_t ws_bytes, void* stream, float* best_eval_ms, float* best_min_ms) {
+    g_err.clear();
+    lj_status s = check_batch(batch, LJ_MAX_ATOMS_EVAL, "lj_autotune");
+    if (s != LJ_OK) return s;
+    if (precision != LJ_FP64 && precision != LJ_MIXED) return fail(LJ_E_ARG, "bad precision");
+    if (batch->num == 0) return LJ_OK;
+    if (batch->total_atoms > 0 && !xyz) return fail(LJ_E_ARG, "xyz is NULL");
+    DeviceInfo di;
+    if ((s = device_info(di)) != LJ_OK) return s;
+    const size_t need = lj_autotune_workspace_bytes(batch, precision);
+    if (!ws || ws_bytes < need)
+        return fail(LJ_E_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    double* e = reinterpret_cast<double*>(w);
+    size_t off = align_up(sizeof(double) * (size_t)batch->num);
+    double* g = reinterpret_cast<double*>(w + off);
+    off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);
+    const int mixed = precision == LJ_MIXED;
+    hipEvent_t e0, e1;
+    LJ_HIP_TRY(hipEventCreate(&e0));
+    LJ_HIP_TRY(hipEventCreate(&e1));
+    auto time_it = [&](auto&& launch, float& ms) -> lj_status {
+        lj_status r = launch();  // warm-up
+        if (r != LJ_OK) return r;
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            LJ_HIP_TRY(hipEventRecord(e0, st));
+            if ((r = launch()) != LJ_OK) return r;
+            LJ_HIP_TRY(hipEventRecord(e1, st));
+            LJ_HIP_TRY(hipEventSynchronize(e1));
+            float t = 0.f;
+            LJ_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            if (t < best) best = t;
+        }
+        ms = best;
+        return LJ_OK;
+    };
+    // pair kernel: every shape holding max_n atoms without more than doubling the padding
+    const int need_slots = batch->max_n < 1 ? 1 : batch->max_n;
+    const int cap = 2 * (pow2_at_least(need_slots) < 64 ? 64 : pow2_at_least(need_slots));
+    lj::EvalShape best_shape = lj::eval_shape(batch->max_n);
+    float best_ms = 1e30f;
+    const int Ws[] = {1, 2, 4, 8, 16}, As[] = {1, 2, 4};
+    for (int wi : Ws)
+        for (int ai : As) {
+            const int slots = 64 * wi * ai;
+            if (slots < need_slots || slots > cap) continue;
+            lj::EvalShape sh{wi, ai};
+            float ms = 0.f;
+            s = time_it([&]() -> lj_status {
+                LJ_HIP_TRY(lj::launch_energy_grad(mixed, sh, batch->num, batch->offset,
+                                                  batch->total_atoms, xyz, e, g, st));
+                return LJ_OK;
+            }, ms);
+            if (s != LJ_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_shape = sh;
+            }
+        }
+    if (s == LJ_OK) {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_eval_sched[{precision, pow2_at_least(need_slots)}] = best_shape;
+    }
+    if (best_eval_ms) *best_eval_ms = best_ms;
+    // large-cluster minimiser: a 3-iteration minimisation of a copy per shape
+    float best_min = -1.f;
+    if (s == LJ_OK && batch->max_n > 256 && batch->max_n <= LJ_MAX_ATOMS_MIN) {
+        double* xc = reinterpret_cast<double*>(w + off);
+        off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);
+        double* outs = reinterpret_cast<double*>(w + off);
+        off = align_up(off + 5 * sizeof(double) * (size_t)batch->num);
+        int32_t* it = reinterpret_cast<int32_t*>(outs + 2 * (size_t)batch->num);
+        int32_t* ev = it + batch->num;
+        int32_t* stt = ev + batch->num;
+        lj_lbfgs_params lp;
+        lj_lbfgs_defaults(&lp);
+        lp.max_iter = 3;
+        lp.polish = 0;
+        int best_k = 0;
+        best_min = 1e30f;
+        for (int k = 0; k < lj::kNumLargeShapes && s == LJ_OK; ++k) {
+            MinLayout L;
+            if ((s = min_layout(batch->num, batch->max_n, mixed, L, k)) != LJ_OK) break;
+            float ms = 0.f;
+            s = time_it([&]() -> lj_status {
+                LJ_HIP_TRY(hipMemcpyAsync(xc, xyz, sizeof(double) * 3 * (size_t)batch->total_atoms,
+                                          hipMemcpyDeviceToDevice, st));
+                return enqueue_minimize(batch, nullptr, xc, outs, outs + batch->num, it, ev, stt,
+                                        nullptr, to_dev(&lp), mixed, L, w + off, st);
+            }, ms);
+            if (s == LJ_OK && ms < best_min) {
+                best_min = ms;
+                best_k = k;
+            }
+        }
+        if (s == LJ_OK) {
+            std::lock_guard<std::mutex> lk(g_sched_mu);
+            g_large_sched[mixed] = best_k;
+        }
+    }
+    if (best_min_ms) *best_min_ms = best_min;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
 }
 
 }  // extern "C"

@@ -167,7 +167,46 @@ __device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<
 // s6 = q^3, and g_i = sum_{j != i} q s6 (24 - 48 s6) (x_i - x_j).
 // ---------------------------------------------------------------------------
 
-// FP64: every operation rounded as written, so the sums are reproducible.
+// One ordered pair (i = slot a of this thread, partner j at p), FP64.  The
+// self pair (r2 = 0) gets q = 0, so it adds exactly zero.
+__device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi, double yi,
+                                          double zi, double& e, double& gx, double& gy,
+                                          double& gz) {
+    const double dx = xi - p.x;
+    const double dy = yi - p.y;
+    const double dz = zi - p.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double q = self ? 0.0 : 1.0 / r2;
+    const double s6 = (q * q) * q;
+    e = e + fma(s6, s6, -s6);
+    const double f = (q * s6) * fma(-48.0, s6, 24.0);
+    gx = fma(f, dx, gx);
+    gy = fma(f, dy, gy);
+    gz = fma(f, dz, gz);
+}
+
+__device__ __forceinline__ void pair_fp32(const float4 p, bool self, float xi, float yi, float zi,
+                                          float& e, float& gx, float& gy, float& gz) {
+    const float dx = xi - p.x;
+    const float dy = yi - p.y;
+    const float dz = zi - p.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float q = self ? 0.0f : __builtin_amdgcn_rcpf(r2);
+    const float s6 = (q * q) * q;
+    e = e + fmaf(s6, s6, -s6);
+    const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+    gx = fmaf(f, dx, gx);
+    gy = fmaf(f, dy, gy);
+    gz = fmaf(f, dz, gz);
+}
+
+// FP64: every operation rounded as written; partners are consumed in
+// ascending order, so each per-atom sum is reproducible.  Partner
+// coordinates are read from LDS in groups of kGroup64 ahead of the
+// arithmetic to cover the LDS latency.
+constexpr int kGroup64 = 4;
+constexpr int kGroup32 = 8;
+
 template <int A, int T>
 __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ pos,
                                            const double (&x)[3][A], double (&e)[A],
@@ -178,23 +217,24 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
         e[a] = 0.0;
         g[0][a] = g[1][a] = g[2][a] = 0.0;
     }
-    for (int j = 0; j < n; ++j) {
-        const double4 pj = pos[j];
+    int j = 0;
+    for (; j + kGroup64 <= n; j += kGroup64) {
+        double4 p[kGroup64];
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-            const double dx = x[0][a] - pj.x;
-            const double dy = x[1][a] - pj.y;
-            const double dz = x[2][a] - pj.z;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            // the self pair (r2 = 0) gets q = 0, so it adds exactly zero
-            const double q = (j == a * T + t) ? 0.0 : 1.0 / r2;
-            const double s6 = (q * q) * q;
-            e[a] = e[a] + fma(s6, s6, -s6);
-            const double f = (q * s6) * fma(-48.0, s6, 24.0);
-            g[0][a] = fma(f, dx, g[0][a]);
-            g[1][a] = fma(f, dy, g[1][a]);
-            g[2][a] = fma(f, dz, g[2][a]);
-        }
+        for (int u = 0; u < kGroup64; ++u) p[u] = pos[j + u];
+#pragma unroll
+        for (int u = 0; u < kGroup64; ++u)
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+                pair_fp64(p[u], j + u == a * T + t, x[0][a], x[1][a], x[2][a], e[a], g[0][a],
+                          g[1][a], g[2][a]);
+    }
+    for (; j < n; ++j) {
+        const double4 p = pos[j];
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+            pair_fp64(p, j == a * T + t, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a],
+                      g[2][a]);
     }
 }
 
@@ -219,22 +259,24 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
         float te[A], tg[3][A];
 #pragma unroll
         for (int a = 0; a < A; ++a) te[a] = tg[0][a] = tg[1][a] = tg[2][a] = 0.0f;
-        for (int j = j0; j < j1; ++j) {
-            const float4 pj = pos[j];
+        int j = j0;
+        for (; j + kGroup32 <= j1; j += kGroup32) {
+            float4 p[kGroup32];
 #pragma unroll
-            for (int a = 0; a < A; ++a) {
-                const float dx = xf[0][a] - pj.x;
-                const float dy = xf[1][a] - pj.y;
-                const float dz = xf[2][a] - pj.z;
-                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                const float q = (j == a * T + t) ? 0.0f : __builtin_amdgcn_rcpf(r2);
-                const float s6 = (q * q) * q;
-                te[a] = te[a] + fmaf(s6, s6, -s6);
-                const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
-                tg[0][a] = fmaf(f, dx, tg[0][a]);
-                tg[1][a] = fmaf(f, dy, tg[1][a]);
-                tg[2][a] = fmaf(f, dz, tg[2][a]);
-            }
+            for (int u = 0; u < kGroup32; ++u) p[u] = pos[j + u];
+#pragma unroll
+            for (int u = 0; u < kGroup32; ++u)
+#pragma unroll
+                for (int a = 0; a < A; ++a)
+                    pair_fp32(p[u], j + u == a * T + t, xf[0][a], xf[1][a], xf[2][a], te[a],
+                              tg[0][a], tg[1][a], tg[2][a]);
+        }
+        for (; j < j1; ++j) {
+            const float4 p = pos[j];
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+                pair_fp32(p, j == a * T + t, xf[0][a], xf[1][a], xf[2][a], te[a], tg[0][a],
+                          tg[1][a], tg[2][a]);
         }
 #pragma unroll
         for (int a = 0; a < A; ++a) {

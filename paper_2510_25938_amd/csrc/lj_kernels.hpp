@@ -52,18 +52,21 @@ struct MinArgs {
 
 // Launchers (lj_minimize.hip, lj_bh_kernels.hip).
 struct EvalShape {
-    int W, A;
+    int W, A;  // wavefronts per workgroup, atom slots per lane
 };
+constexpr int kNumLargeShapes = 3;  // minimiser shapes for N in 257..1024
 EvalShape eval_shape(int max_n);
-hipError_t launch_energy_grad(int mixed, int max_n, int num, const int32_t* off, int64_t total,
+bool eval_shape_supported(EvalShape s);
+hipError_t launch_energy_grad(int mixed, EvalShape s, int num, const int32_t* off, int64_t total,
                               const double* xyz, double* e, double* g, hipStream_t st);
 int class_of(int n);
-int class_block(int c);
-size_t class_hist_bytes_per_wg(int c);
-const void* minimize_kernel_for(int mixed, int c);
+int class_block(int c, int large);
+size_t class_hist_bytes_per_wg(int c, int large);
+const void* minimize_kernel_for(int mixed, int c, int large);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);
-hipError_t launch_minimize_class(int mixed, int c, int grid, const MinArgs& a, hipStream_t st);
+hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,
+                                 hipStream_t st);
 
 struct BhDev {
     int cands;

@@ -599,6 +599,12 @@ EvalShape eval_shape(int max_n) {
     return {16, 4};
 }
 
+bool eval_shape_supported(EvalShape s) {
+    const bool w = s.W == 1 || s.W == 2 || s.W == 4 || s.W == 8 || s.W == 16;
+    const bool a = s.A == 1 || s.A == 2 || s.A == 4;
+    return w && a;
+}
+
 template <int MIXED>
 static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_t total,
                                 const double* xyz, double* e, double* g, hipStream_t st) {
@@ -614,27 +620,41 @@ static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_
     LJ_EVAL_CASE(4, 1)
     LJ_EVAL_CASE(8, 1)
     LJ_EVAL_CASE(16, 1)
+    LJ_EVAL_CASE(1, 2)
+    LJ_EVAL_CASE(2, 2)
+    LJ_EVAL_CASE(4, 2)
+    LJ_EVAL_CASE(8, 2)
     LJ_EVAL_CASE(16, 2)
+    LJ_EVAL_CASE(1, 4)
+    LJ_EVAL_CASE(2, 4)
+    LJ_EVAL_CASE(4, 4)
+    LJ_EVAL_CASE(8, 4)
     LJ_EVAL_CASE(16, 4)
 #undef LJ_EVAL_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_energy_grad(int mixed, int max_n, int num, const int32_t* off, int64_t total,
+hipError_t launch_energy_grad(int mixed, EvalShape s, int num, const int32_t* off, int64_t total,
                               const double* xyz, double* e, double* g, hipStream_t st) {
-    const EvalShape s = eval_shape(max_n);
     return mixed ? launch_eval_t<1>(s, num, off, total, xyz, e, g, st)
                  : launch_eval_t<0>(s, num, off, total, xyz, e, g, st);
 }
 
-// Minimiser class shapes: classes 0-2 keep the history in registers
-// (one, two, four wavefronts); class 3 uses 16 wavefronts and a global ring.
+// Minimiser shapes.  Classes 0-2 keep the history in registers (one, two,
+// four wavefronts, one atom per lane).  Class 3 (N in 257..1024) keeps it in a
+// global ring and has three interchangeable shapes of 1024 atom slots:
+// 16 wavefronts x 1 atom, 8 x 2, 4 x 4 (chosen by the schedule table).
 struct ClassShape {
     int W, A;
     bool hreg;
 };
 constexpr ClassShape kClassShape[kNumClasses] = {{1, 1, true}, {2, 1, true}, {4, 1, true},
                                                  {16, 1, false}};
+constexpr ClassShape kLargeShape[kNumLargeShapes] = {{16, 1, false}, {8, 2, false}, {4, 4, false}};
+
+static ClassShape shape_of(int c, int large) {
+    return c == 3 ? kLargeShape[large] : kClassShape[c];
+}
 
 int class_of(int n) {
     for (int c = 0; c < kNumClasses; ++c)
@@ -642,8 +662,8 @@ int class_of(int n) {
     return -1;
 }
 
-size_t class_hist_bytes_per_wg(int c) {
-    const ClassShape s = kClassShape[c];
+size_t class_hist_bytes_per_wg(int c, int large) {
+    const ClassShape s = shape_of(c, large);
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
@@ -652,21 +672,30 @@ static const void* min_kernel_ptr() {
     return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG>);
 }
 
-const void* minimize_kernel_for(int mixed, int c) {
-    switch (c * 2 + (mixed ? 1 : 0)) {
-        case 0: return min_kernel_ptr<0, 1, 1, true>();
-        case 1: return min_kernel_ptr<1, 1, 1, true>();
-        case 2: return min_kernel_ptr<0, 2, 1, true>();
-        case 3: return min_kernel_ptr<1, 2, 1, true>();
-        case 4: return min_kernel_ptr<0, 4, 1, true>();
-        case 5: return min_kernel_ptr<1, 4, 1, true>();
-        case 6: return min_kernel_ptr<0, 16, 1, false>();
-        case 7: return min_kernel_ptr<1, 16, 1, false>();
+const void* minimize_kernel_for(int mixed, int c, int large) {
+    if (c < 3) {
+        switch (c * 2 + (mixed ? 1 : 0)) {
+            case 0: return min_kernel_ptr<0, 1, 1, true>();
+            case 1: return min_kernel_ptr<1, 1, 1, true>();
+            case 2: return min_kernel_ptr<0, 2, 1, true>();
+            case 3: return min_kernel_ptr<1, 2, 1, true>();
+            case 4: return min_kernel_ptr<0, 4, 1, true>();
+            case 5: return min_kernel_ptr<1, 4, 1, true>();
+        }
+        return nullptr;
+    }
+    switch (large * 2 + (mixed ? 1 : 0)) {
+        case 0: return min_kernel_ptr<0, 16, 1, false>();
+        case 1: return min_kernel_ptr<1, 16, 1, false>();
+        case 2: return min_kernel_ptr<0, 8, 2, false>();
+        case 3: return min_kernel_ptr<1, 8, 2, false>();
+        case 4: return min_kernel_ptr<0, 4, 4, false>();
+        case 5: return min_kernel_ptr<1, 4, 4, false>();
     }
     return nullptr;
 }
 
-int class_block(int c) { return kWave * kClassShape[c].W; }
+int class_block(int c, int large) { return kWave * shape_of(c, large).W; }
 
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st) {
@@ -675,11 +704,12 @@ hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_minimize_class(int mixed, int c, int grid, const MinArgs& a, hipStream_t st) {
-    const void* k = minimize_kernel_for(mixed, c);
+hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,
+                                 hipStream_t st) {
+    const void* k = minimize_kernel_for(mixed, c, large);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {const_cast<MinArgs*>(&a)};
-    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c)), args, 0, st);
+    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large)), args, 0, st);
 }
 
 }  // namespace lj

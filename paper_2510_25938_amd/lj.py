@@ -18,8 +18,10 @@ FP64, MIXED = 0, 1
 CONVERGED, MAXITER, LSFAIL, NONFINITE, SWITCHED, BADSIZE = 0, 1, 2, 3, 4, 5
 OK, E_ARG, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_ATOMS_EVAL, MAX_ATOMS_MIN, MAX_M, MAX_CANDS = 4096, 1024, 10, 64
+SCHED_EVAL, SCHED_MIN_LARGE = 0, 1
 EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
-            "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_status_string",
+            "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_set_schedule",
+            "lj_get_schedule", "lj_autotune_workspace_bytes", "lj_autotune", "lj_status_string",
             "lj_last_error", "lj_abi_version"]
 
 
@@ -81,6 +83,15 @@ def lib():
                                  C.POINTER(LbfgsParams), i32, i32, C.POINTER(BhTrace), vp,
                                  C.c_size_t, vp]
         L.lj_bh_step.restype = i32
+        L.lj_set_schedule.argtypes = [i32, i32, i32, i32, i32]
+        L.lj_set_schedule.restype = i32
+        L.lj_get_schedule.argtypes = [i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.lj_get_schedule.restype = i32
+        L.lj_autotune_workspace_bytes.argtypes = [C.POINTER(Batch), i32]
+        L.lj_autotune_workspace_bytes.restype = C.c_size_t
+        L.lj_autotune.argtypes = [C.POINTER(Batch), vp, i32, vp, C.c_size_t, vp,
+                                  C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.lj_autotune.restype = i32
         L.lj_status_string.argtypes = [i32]
         L.lj_status_string.restype = C.c_char_p
         L.lj_last_error.argtypes = []
@@ -182,6 +193,77 @@ def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, work
                                       C.byref(params), precision_code(precision),
                                       _ptr(workspace), workspace.numel(), _stream(stream)))
     return out
+
+
+def set_schedule(kind, precision, max_n, w, a=1):
+    _check(lib().lj_set_schedule(kind, precision_code(precision), int(max_n), int(w), int(a)))
+
+
+def eval_shape_default(max_n):
+    """The library's built-in pair-kernel shape (W, A) for max_n atoms."""
+    n = max(int(max_n), 1)
+    for lim, shape in ((64, (1, 1)), (128, (2, 1)), (256, (4, 1)), (512, (8, 1)),
+                       (1024, (16, 1)), (2048, (16, 2))):
+        if n <= lim:
+            return shape
+    return (16, 4)
+
+
+def get_schedule(kind, precision, max_n=0):
+    w, a = C.c_int32(), C.c_int32()
+    _check(lib().lj_get_schedule(kind, precision_code(precision), int(max_n), C.byref(w),
+                                 C.byref(a)))
+    return w.value, a.value
+
+
+def autotune(batch, xyz, precision="mixed", stream=None, cache=None):
+    """Time every launch schedule for this batch shape and keep the fastest.
+
+    Synchronises the stream.  With `cache` (a JSON path) the chosen schedules
+    are merged into that file; `load_schedules` installs them in a new process.
+    Returns {"eval": (W, A, ms), "min_large": (shape, ms) or None}.
+    """
+    prec = precision_code(precision)
+    nb = int(lib().lj_autotune_workspace_bytes(C.byref(batch.desc()), prec))
+    if nb == 0:
+        _check(E_ARG)
+    ws = torch.empty(nb, dtype=torch.uint8, device=xyz.device)
+    t_eval, t_min = C.c_float(), C.c_float()
+    _check(lib().lj_autotune(C.byref(batch.desc()), _ptr(xyz), prec, _ptr(ws), nb,
+                             _stream(stream), C.byref(t_eval), C.byref(t_min)))
+    w, a = get_schedule(SCHED_EVAL, prec, batch.max_n)
+    res = {"eval": (w, a, t_eval.value), "min_large": None}
+    if t_min.value >= 0:
+        res["min_large"] = (get_schedule(SCHED_MIN_LARGE, prec)[0], t_min.value)
+    if cache:
+        import json
+        table = {}
+        if os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        key = "fp64" if prec == FP64 else "mixed"
+        p2 = 1
+        while p2 < max(batch.max_n, 1):
+            p2 *= 2
+        table.setdefault(key, {}).setdefault("eval", {})[str(p2)] = [w, a]
+        if res["min_large"] is not None:
+            table[key]["min_large"] = res["min_large"][0]
+        with open(cache, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+    return res
+
+
+def load_schedules(cache):
+    """Install schedules saved by `autotune(..., cache=path)`."""
+    import json
+    with open(cache) as fh:
+        table = json.load(fh)
+    for key, entry in table.items():
+        prec = FP64 if key == "fp64" else MIXED
+        for p2, (w, a) in entry.get("eval", {}).items():
+            set_schedule(SCHED_EVAL, prec, int(p2), w, a)
+        if "min_large" in entry:
+            set_schedule(SCHED_MIN_LARGE, prec, 0, entry["min_large"], 0)
 
 
 def bh_params(cands=8, kT=0.8, adapt_interval=10, target_rate=0.5, factor=0.9, seed=0):

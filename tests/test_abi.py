@@ -87,3 +87,20 @@ def test_cluster_batch_validation():
         lj.ClusterBatch([0, 5, 3], device="cpu")
     b = lj.ClusterBatch([0, 13, 13, 51], device="cpu")
     assert b.num == 3 and b.max_n == 38 and b.total == 51 and list(b.sizes) == [13, 0, 38]
+
+
+def test_schedule_table_validation():
+    L = lj.lib()
+    assert L.lj_set_schedule(lj.SCHED_EVAL, lj.FP64, 1000, 3, 1) == lj.E_ARG  # W = 3
+    assert L.lj_set_schedule(lj.SCHED_EVAL, lj.FP64, 1000, 4, 2) == lj.E_ARG  # 512 slots
+    assert L.lj_set_schedule(lj.SCHED_MIN_LARGE, lj.MIXED, 0, 3, 0) == lj.E_ARG
+    assert L.lj_set_schedule(7, lj.FP64, 10, 1, 1) == lj.E_ARG
+    assert lj.get_schedule(lj.SCHED_EVAL, "fp64", 1000) == (16, 1)  # built-in rule
+    lj.set_schedule(lj.SCHED_EVAL, "fp64", 1000, 4, 4)
+    assert lj.get_schedule(lj.SCHED_EVAL, "fp64", 1000) == (4, 4)
+    assert lj.get_schedule(lj.SCHED_EVAL, "fp64", 600) == (4, 4)  # same power-of-two key
+    assert lj.get_schedule(lj.SCHED_EVAL, "mixed", 1000) == (16, 1)
+    lj.set_schedule(lj.SCHED_EVAL, "fp64", 1000, 16, 1)
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 2)
+    assert lj.get_schedule(lj.SCHED_MIN_LARGE, "mixed")[0] == 2
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 0)

@@ -102,3 +102,55 @@ def test_deterministic_repeat():
         E1, g1 = lj.energy_grad(b, xd, prec)
         E2, g2 = lj.energy_grad(b, xd, prec)
         assert torch.equal(E1, E2) and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("sizes", [[1000, 700, 13], [200, 150], [3000, 2100]])
+def test_every_schedule_gives_identical_fp64(sizes):
+    """FP64 results do not depend on the workgroup shape (fixed summation order)."""
+    off, x = random_starts(sizes, 300 + sizes[0])
+    b, xd = to_dev(off, x)
+    Eo, go = O.energy_grad(off, x)
+    p2 = 1
+    while p2 < b.max_n:
+        p2 *= 2
+    shapes = [(w, a) for w in (1, 2, 4, 8, 16) for a in (1, 2, 4)
+              if b.max_n <= 64 * w * a <= 2 * max(64, p2)]
+    assert len(shapes) >= 2
+    try:
+        for w, a in shapes:
+            announce(f"eval schedule W={w} A={a} sizes={sizes}")
+            lj.set_schedule(lj.SCHED_EVAL, "fp64", b.max_n, w, a)
+            E, g = lj.energy_grad(b, xd, "fp64")
+            assert np.array_equal(host(E), Eo) and np.array_equal(host(g), go), (w, a)
+    finally:
+        lj.set_schedule(lj.SCHED_EVAL, "fp64", b.max_n, *lj.eval_shape_default(b.max_n))
+
+
+def test_autotune_installs_a_valid_schedule(tmp_path):
+    off, x = random_starts([1000] * 64, 77)
+    b, xd = to_dev(off, x)
+    announce("autotune 64 x LJ1000 mixed")
+    res = lj.autotune(b, xd, "mixed", cache=str(tmp_path / "sched.json"))
+    w, a, ms = res["eval"]
+    assert 64 * w * a >= 1000 and ms > 0
+    assert res["min_large"] is not None and res["min_large"][0] in (0, 1, 2)
+    E, g = lj.energy_grad(b, xd, "mixed")
+    Eo, go = O.energy_grad(off, x.astype(np.float32).astype(np.float64))
+    eabs, gabs = O.abs_sums(off, x.astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(host(E) - Eo) <= 128 * U32 * eabs)
+    lj.load_schedules(str(tmp_path / "sched.json"))
+    assert lj.get_schedule(lj.SCHED_EVAL, "mixed", 1000)[:2] == (w, a)
+    # the tuned minimiser shape gives the same FP64 result as the default one
+    p = lj.lbfgs_params(max_iter=20)
+    sub_off, sub_x = random_starts([300, 500], 78)
+    bs, xs = to_dev(sub_off, sub_x)
+    ref = None
+    for k in range(3):
+        lj.set_schedule(lj.SCHED_MIN_LARGE, "fp64", 0, k)
+        r = lj.minimize(bs, xs, p, "fp64")
+        r = {kk: host(v) for kk, v in r.items() if v is not None}
+        if ref is None:
+            ref = r
+        for kk in ("xyz", "energy", "iters", "evals", "status"):
+            assert np.array_equal(r[kk], ref[kk]), (k, kk)
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "fp64", 0, 0)
