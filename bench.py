@@ -50,6 +50,36 @@ def load_traffic(key):
     return t[key]["hbm_bytes_per_launch"]
 
 
+def pair_kernel(lj, large_clusters, dev, stream, torch):
+    """lj_energy_grad_batch on 256 clusters of N = 1000, FP32-pair and FP64."""
+    wl4 = large_clusters()
+    off4, x4 = wl4.starts()
+    b4 = lj.ClusterBatch(off4, device=dev)
+    x4d = torch.from_numpy(x4).to(dev)
+    out = {}
+    for prec, peak in (("mixed", PEAK_FP32), ("fp64", PEAK_FP64)):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                lj.energy_grad(b4, x4d, prec, stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(stream)
+            for _ in range(reps):
+                lj.energy_grad(b4, x4d, prec, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        pairs = b4.num * 1000 * 999 / 2
+        flops = FLOP_PER_PAIR * pairs
+        w, a = lj.get_schedule(lj.SCHED_EVAL, prec, 1000)
+        out[prec] = {"workload": "256 x LJ1000 energy+gradient", "schedule": f"{w} waves x {a} atoms",
+                     "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3),
+                     "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                     "peak_tflops": peak / 1e12, "frac_of_peak": flops / (ms * 1e-3) / peak}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,6 +88,11 @@ def main():
     ap.add_argument("--count", type=int, default=1024, help="LJ38 clusters per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-pair", action="store_true", help="skip the standalone pair kernel")
+    ap.add_argument("--only", choices=["mixed", "fp64", "pair"],
+                    help="run one leg only and print its timing (for profiler runs)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run a plain 256 MiB device-to-device copy 5 times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -73,6 +108,17 @@ def main():
     dev = "cuda"
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.copy_ref:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            for _ in range(5):
+                dst.copy_(src)
+        stream.synchronize()
+        print(json.dumps({"copy_ref_bytes_read": nbytes, "copy_ref_bytes_written": nbytes,
+                          "launches": 5}), flush=True)
+        return
     wl = lj38_batch(args.count)
     off, x = wl.starts()
     n = 38
@@ -109,9 +155,18 @@ def main():
         pair_evals = int(evals.sum()) * pairs_per_eval
         return dict(wall=wall, kern_ms=kern_ms, host=host, pair_evals=pair_evals)
 
-    mixed = run("mixed", args.steps, args.warmup)
-    fp64 = run("fp64", args.steps, args.warmup)
     B = batch.num
+    if args.only in ("mixed", "fp64"):
+        r = run(args.only, args.steps, args.warmup)
+        print(json.dumps({"only": args.only, "kernel_ms": r["kern_ms"],
+                          "minimisations_per_s": B * args.steps / r["wall"],
+                          "pair_evals_per_launch": r["pair_evals"]}), flush=True)
+        return
+    if args.only == "pair":
+        args.no_cpu = True
+    else:
+        mixed = run("mixed", args.steps, args.warmup)
+        fp64 = run("fp64", args.steps, args.warmup)
 
     def summary(r):
         st = r["host"]["status"]
@@ -125,6 +180,10 @@ def main():
                     median_evals=float(np.median(r["host"]["evals"])),
                     mean_energy=float(np.mean(r["host"]["energy"])))
 
+    if args.only == "pair":
+        pair = pair_kernel(lj, large_clusters, dev, stream, torch)
+        print(json.dumps({"only": "pair", "pair_kernel": pair}), flush=True)
+        return
     sm, s64 = summary(mixed), summary(fp64)
 
     # Sampled parity against the oracle (FP64: bitwise; mixed: same-minimum rate).
@@ -148,31 +207,7 @@ def main():
         parity["mixed_energy_rel_err_median"] = float(np.median(rel))
 
     # Standalone pair kernel: 256 clusters of N = 1000.
-    pair = None
-    if not args.no_pair:
-        wl4 = large_clusters()
-        off4, x4 = wl4.starts()
-        b4 = lj.ClusterBatch(off4, device=dev)
-        x4d = torch.from_numpy(x4).to(dev)
-        pair = {}
-        for prec, peak in (("mixed", PEAK_FP32), ("fp64", PEAK_FP64)):
-            with torch.cuda.stream(stream):
-                for _ in range(3):
-                    lj.energy_grad(b4, x4d, prec, stream=stream)
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                reps = 20
-                e0.record(stream)
-                for _ in range(reps):
-                    lj.energy_grad(b4, x4d, prec, stream=stream)
-                e1.record(stream)
-                stream.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            flops = FLOP_PER_PAIR * b4.num * 1000 * 999 / 2
-            pair[prec] = {"workload": "256 x LJ1000 energy+gradient", "ms": ms,
-                          "pair_evals_per_s": b4.num * 1000 * 999 / 2 / (ms * 1e-3),
-                          "achieved_tflops": flops / (ms * 1e-3) / 1e12,
-                          "frac_of_peak": flops / (ms * 1e-3) / peak}
+    pair = None if args.no_pair else pair_kernel(lj, large_clusters, dev, stream, torch)
 
     # Roofline of the dominant kernel (the persistent minimiser, mixed path):
     # algorithmic FLOP = 27 per unique pair evaluation over every evaluation of

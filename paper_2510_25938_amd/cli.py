@@ -1,0 +1,73 @@
+"""Command line: adaptive, parallel basin hopping of one LJ cluster on the GPU.
+
+    python -m paper_2510_25938_amd.cli input.molden [--steps 200] [--cands 8]
+        [--kT 1.0] [--step0 0.4] [--precision fp64|mixed] [--seed S]
+
+Reads the first geometry of input.molden (Methodology, "Initial Structures
+and Input"), minimises it, runs the basin-hopping loop of the Algorithm
+Overview (perturb, n candidates minimised together, select, Metropolis,
+adapt every 10 steps toward 50 % acceptance) through lj_bh_step, and writes
+every accepted structure to input_accepted.molden (Running the Code).  Prints
+one line per step: trial energy, decision, lowest energy so far, step size.
+"""
+import argparse
+import os
+import sys
+
+import numpy as np
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("molden")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--cands", type=int, default=8)
+    ap.add_argument("--kT", type=float, default=1.0)
+    ap.add_argument("--step0", type=float, default=0.4)
+    ap.add_argument("--interval", type=int, default=10)
+    ap.add_argument("--target", type=float, default=0.5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--seed", type=int, default=2510)
+    ap.add_argument("--sigma", type=float, default=1.0,
+                    help="length unit of the file in LJ sigma (coordinates are divided by it)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import lj
+    from .inputs import aos_to_planes, planes_to_aos
+    from .molden import read_first_geometry, write_geometries
+
+    flat, syms = read_first_geometry(args.molden)
+    n = len(syms)
+    x = aos_to_planes(flat / args.sigma)
+    batch = lj.ClusterBatch(np.array([0, n], np.int32))
+    xd = torch.from_numpy(x).to("cuda")
+    params = lj.lbfgs_params()
+    r = lj.minimize(batch, xd, params, "fp64")
+    bh = lj.bh_params(cands=args.cands, kT=args.kT, adapt_interval=args.interval,
+                      target_rate=args.target, seed=args.seed)
+    chain = lj.BasinHopping(batch, r["xyz"], r["energy"], bh, params, args.precision,
+                            step0=args.step0, trace_steps=args.steps)
+    frames, energies = [], []
+    for k in range(args.steps):
+        chain.step(1)
+        torch.cuda.synchronize()
+        acc = int(chain.trace["accepted"][0, k].item())
+        if acc:
+            frames.append(planes_to_aos(chain.xyz_cur.cpu().numpy()) * args.sigma)
+            energies.append(float(chain.e_cur[0].item()))
+        if not args.quiet:
+            print(f"step {k + 1:5d}  E_trial {chain.trace['e_trial'][0, k].item():14.8f}  "
+                  f"{'accept' if acc else 'reject'}  E_low {chain.trace['e_best'][0, k].item():14.8f}"
+                  f"  s {chain.trace['step'][0, k].item():.5f}", flush=True)
+    out = os.path.splitext(args.molden)[0] + "_accepted.molden"
+    write_geometries(out, frames, energies, syms)
+    print(f"{len(frames)} accepted structures -> {out}; lowest accepted "
+          f"{chain.e_best_acc[0].item():.8f}", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -40,8 +40,8 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
     int2 b = *reinterpret_cast<int2*>(&v);
-    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, CTRL, 0xF, 0xF, false);
-    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, CTRL, 0xF, 0xF, false);
+    b.x = __builtin_amdgcn_mov_dpp(b.x, CTRL, 0xF, 0xF, true);
+    b.y = __builtin_amdgcn_mov_dpp(b.y, CTRL, 0xF, 0xF, true);
     return *reinterpret_cast<double*>(&b);
 }
 
