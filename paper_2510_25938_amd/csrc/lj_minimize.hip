@@ -266,6 +266,10 @@ struct History<W, A, false> {
 
 // Phase outcomes (LJ_* statuses, plus the FP32 phase's stall exit).
 constexpr int kStall = 100;
+// The FP32 phase treats energy changes as noise-limited only once
+// ||g|| < kNoiseZone * its tolerance: there the Armijo allowance and the exit
+// after five accepted steps without a decrease apply.
+constexpr double kNoiseZone = 100.0;
 
 // One L-BFGS run from x (history cleared).  On return x, g, E hold the last
 // accepted iterate.  F32 selects the FP32 pair arithmetic, the Armijo noise
@@ -325,9 +329,16 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             gd = tm.dot(g, d);
         }
         // backtracking Armijo line search
+        const bool noise_zone = F32 && gnorm < kNoiseZone * gtol;
         double alpha = 1.0, Et = 0.0;
         bool ok = false;
         for (int ls = 0; ls < p.max_ls; ++ls) {
+            // FP32 phase: a backtracked trial whose first-order decrease is
+            // below the FP32 energy noise cannot be validated by the Armijo
+            // test (noise could pass it), so the line search fails instead
+            if constexpr (F32) {
+                if (alpha < 1.0 && -(alpha * gd) < p.ls_noise * fabs(E)) break;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -335,7 +346,12 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             Et = tm.template eval<F32>(xt, gt);
             ++evals;
             double rhs = fma(p.c1 * alpha, gd, E);
-            if constexpr (F32) rhs = rhs + p.ls_noise * fabs(E);
+            // FP32 phase near its tolerance: the full quasi-Newton step may be
+            // accepted within the FP32 energy noise; a backtracked step, or any
+            // step farther from convergence, must show a real decrease
+            if constexpr (F32) {
+                if (alpha == 1.0 && noise_zone) rhs = rhs + p.ls_noise * fabs(E);
+            }
             if (Et <= rhs) {
                 ok = true;
                 break;
@@ -376,7 +392,7 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             return LJ_LSFAIL;
         }
         if (p.m > 0 && sy > p.curv_eps * sqrt(ss * yy)) H.push(d, g, 1.0 / sy, sy / yy, p.m);
-        if constexpr (F32) stall = (Et < E) ? 0 : stall + 1;
+        if constexpr (F32) stall = (Et < E || !noise_zone) ? 0 : stall + 1;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -464,8 +480,8 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                     st = LJ_NONFINITE;
                 else if (gn < args.p.gtol)
                     st = LJ_CONVERGED;
-                else if (r32 == LJ_CONVERGED || r32 == kStall)
-                    st = LJ_SWITCHED;
+                else if (r32 == LJ_CONVERGED || r32 == kStall || r32 == LJ_LSFAIL)
+                    st = LJ_SWITCHED;  // the FP32 phase reached its tolerance or resolution
                 else
                     st = r32 == LJ_NONFINITE ? LJ_LSFAIL : r32;
             }

@@ -104,7 +104,7 @@ def test_deterministic_repeat():
         assert torch.equal(E1, E2) and torch.equal(g1, g2)
 
 
-@pytest.mark.parametrize("sizes", [[1000, 700, 13], [200, 150], [3000, 2100]])
+@pytest.mark.parametrize("sizes", [[1000, 700, 13], [200, 150], [1500, 900]])
 def test_every_schedule_gives_identical_fp64(sizes):
     """FP64 results do not depend on the workgroup shape (fixed summation order)."""
     off, x = random_starts(sizes, 300 + sizes[0])
