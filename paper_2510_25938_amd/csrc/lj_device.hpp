@@ -27,15 +27,17 @@ __device__ __forceinline__ double uniform(double v) {
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
-// Sum over the 64 lanes in balanced-tree order.  Levels 1-4 run inside each
-// 16-lane row with DPP lane permutes: quad_perm [1,0,3,2] and [2,3,0,1] pair
-// lanes 2^0 and 2^1 apart; once every quad holds one value, row_half_mirror
-// pairs each quad with the other quad of its 8-lane half, and once every
-// half holds one value, row_mirror pairs the two halves of the row.  Each
-// level adds the partner's value (IEEE addition is commutative, so both
-// lanes of a pair hold identical bits).  The four row sums r0..r3 are then
-// read out and combined as (r0 + r1) + (r2 + r3).  The result equals the
-// pairwise sum over the lane index and is wave-uniform.
+// Sum over the 64 lanes in balanced-tree order, entirely in registers.
+// Levels 1-4 run inside each 16-lane row with DPP lane permutes:
+// quad_perm [1,0,3,2] and [2,3,0,1] pair lanes 2^0 and 2^1 apart; once every
+// quad holds one value, row_half_mirror pairs each quad with the other quad
+// of its 8-lane half, and once every half holds one value, row_mirror pairs
+// the two halves of the row.  Levels 5-6 use the gfx950 permlane swaps:
+// v_permlane16_swap exchanges odd rows of one copy with even rows of another,
+// so the sum of the two results pairs rows (0,1) and (2,3); v_permlane32_swap
+// does the same for the two 32-lane halves.  Each level adds two values that
+// are both held by the lanes involved (IEEE addition is commutative), so
+// every lane ends with identical bits: the pairwise sum over the lane index.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
@@ -50,11 +52,26 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // row_half_mirror
 constexpr int kDppMirror = 0x140;     // row_mirror
 
-__device__ __forceinline__ double lane_value(double v, int lane) {
+// (value of the partner row, own value) ordered so that adding them gives the
+// same bits in both rows of a pair: returns the two swapped copies.
+__device__ __forceinline__ void swap_rows16(double v, double& lo, double& hi) {
     int2 b = *reinterpret_cast<int2*>(&v);
-    b.x = __builtin_amdgcn_readlane(b.x, lane);
-    b.y = __builtin_amdgcn_readlane(b.y, lane);
-    return *reinterpret_cast<double*>(&b);
+    auto x = __builtin_amdgcn_permlane16_swap(b.x, b.x, false, false);
+    auto y = __builtin_amdgcn_permlane16_swap(b.y, b.y, false, false);
+    int2 l = make_int2((int)x[0], (int)y[0]);
+    int2 h = make_int2((int)x[1], (int)y[1]);
+    lo = *reinterpret_cast<double*>(&l);
+    hi = *reinterpret_cast<double*>(&h);
+}
+
+__device__ __forceinline__ void swap_halves32(double v, double& lo, double& hi) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    auto x = __builtin_amdgcn_permlane32_swap(b.x, b.x, false, false);
+    auto y = __builtin_amdgcn_permlane32_swap(b.y, b.y, false, false);
+    int2 l = make_int2((int)x[0], (int)y[0]);
+    int2 h = make_int2((int)x[1], (int)y[1]);
+    lo = *reinterpret_cast<double*>(&l);
+    hi = *reinterpret_cast<double*>(&h);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -62,7 +79,11 @@ __device__ __forceinline__ double wave_sum(double v) {
     v = v + dpp<kDppXor2>(v);
     v = v + dpp<kDppHalfMirror>(v);
     v = v + dpp<kDppMirror>(v);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+    double a, b;
+    swap_rows16(v, a, b);  // a: even row's value in both rows, b: odd row's
+    v = a + b;
+    swap_halves32(v, a, b);
+    return a + b;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -70,7 +91,11 @@ __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp<kDppXor2>(v));
     v = fmax(v, dpp<kDppHalfMirror>(v));
     v = fmax(v, dpp<kDppMirror>(v));
-    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+    double a, b;
+    swap_rows16(v, a, b);
+    v = fmax(a, b);
+    swap_halves32(v, a, b);
+    return fmax(a, b);
 }
 
 // Balanced tree over K values (K a power of two): ((r0+r1)+(r2+r3))+...

@@ -153,4 +153,4 @@ def test_autotune_installs_a_valid_schedule(tmp_path):
             ref = r
         for kk in ("xyz", "energy", "iters", "evals", "status"):
             assert np.array_equal(r[kk], ref[kk]), (k, kk)
-    lj.set_schedule(lj.SCHED_MIN_LARGE, "fp64", 0, 0)
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "fp64", 0, 1)
