@@ -137,6 +137,10 @@ size_t lj_minimize_workspace_bytes(const lj_batch* batch, const lj_lbfgs_params*
  *   xyz_switch [3][total_atoms] device or NULL: LJ_MIXED only, the point where
  *             the FP32 phase ended (the polish starts there).
  *   ws, ws_bytes  workspace of at least lj_minimize_workspace_bytes().
+ * Clusters are planned on `stream` (sorted by N, largest first, into size
+ * classes); with more than one class present, the classes run concurrently on
+ * library-owned side streams forked from and joined back into `stream` with
+ * events (also under stream capture, as parallel graph branches).
  * The result of each cluster depends only on its own start and the
  * parameters, never on the batch composition or the launch schedule.
  * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED (max_n > LJ_MAX_ATOMS_MIN), LJ_E_WORKSPACE,

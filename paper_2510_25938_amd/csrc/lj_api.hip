@@ -183,6 +183,39 @@ lj_status min_layout(int num, int max_n, int mixed, MinLayout& L, int large = -1
     return LJ_OK;
 }
 
+// Per-device side streams (default priority) and events used to run the
+// minimiser's size classes concurrently: fork from the caller's stream after
+// the plan kernel, one class per side stream, join back before returning.
+// The pattern is also valid under stream capture (parallel graph branches).
+struct SideStreams {
+    bool ready = false;
+    hipStream_t s[lj::kNumClasses];
+    hipEvent_t fork;
+    hipEvent_t join[lj::kNumClasses];
+    std::mutex mu;
+};
+std::mutex g_side_mu;
+std::vector<SideStreams*> g_side;
+
+lj_status side_streams(SideStreams*& out) {
+    int dev = 0;
+    LJ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if ((int)g_side.size() <= dev) g_side.resize(dev + 1, nullptr);
+    if (!g_side[dev]) g_side[dev] = new SideStreams();  // lives until the process ends
+    SideStreams* ss = g_side[dev];
+    if (!ss->ready) {
+        for (int c = 0; c < lj::kNumClasses; ++c) {
+            LJ_HIP_TRY(hipStreamCreateWithFlags(&ss->s[c], hipStreamNonBlocking));
+            LJ_HIP_TRY(hipEventCreateWithFlags(&ss->join[c], hipEventDisableTiming));
+        }
+        LJ_HIP_TRY(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
+        ss->ready = true;
+    }
+    out = ss;
+    return LJ_OK;
+}
+
 lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz, double* energy,
                            double* gnorm, int32_t* iters, int32_t* evals, int32_t* status,
                            double* xyz_switch, const lj::LbfgsDev& p, int mixed,
@@ -205,11 +238,26 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     a.xyz_switch = mixed ? xyz_switch : nullptr;
     a.plan = plan;
     a.p = p;
+    if (L.top_class == 0) {
+        a.cls = 0;
+        a.hist = nullptr;
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, 0, L.large, L.grid[0], a, st));
+        return LJ_OK;
+    }
+    // several size classes: run them concurrently on side streams
+    SideStreams* ss = nullptr;
+    lj_status r = side_streams(ss);
+    if (r != LJ_OK) return r;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    LJ_HIP_TRY(hipEventRecord(ss->fork, st));
     for (int c = L.top_class; c >= 0; --c) {  // largest clusters first
         a.cls = c;
         a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.grid[c], a, st));
+        LJ_HIP_TRY(hipStreamWaitEvent(ss->s[c], ss->fork, 0));
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.grid[c], a, ss->s[c]));
+        LJ_HIP_TRY(hipEventRecord(ss->join[c], ss->s[c]));
     }
+    for (int c = L.top_class; c >= 0; --c) LJ_HIP_TRY(hipStreamWaitEvent(st, ss->join[c], 0));
     return LJ_OK;
 }
 

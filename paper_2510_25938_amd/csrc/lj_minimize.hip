@@ -270,21 +270,39 @@ constexpr int kStall = 100;
 // ||g|| < kNoiseZone * its tolerance: there the Armijo allowance and the exit
 // after five accepted steps without a decrease apply.
 constexpr double kNoiseZone = 100.0;
+// Inside the noise zone the FP32 phase also ends after kZonePatience accepted
+// steps without lowering the best gradient norm of the zone by 10 %.
+constexpr int kZonePatience = 30;
+
+// E and g at x with FP32 pair arithmetic when f32 (only compiled when CAN32).
+template <bool CAN32, int W, int A>
+__device__ __forceinline__ double eval_phase(Team<W, A>& tm, const double (&x)[3][A],
+                                             double (&g)[3][A], bool f32) {
+    if constexpr (CAN32) {
+        if (f32) return tm.template eval<true>(x, g);
+    }
+    return tm.template eval<false>(x, g);
+}
 
 // One L-BFGS run from x (history cleared).  On return x, g, E hold the last
-// accepted iterate.  F32 selects the FP32 pair arithmetic, the Armijo noise
-// allowance and the stall exit of the mixed path's first phase.
-template <bool F32, int W, int A, bool HREG>
+// accepted iterate.  f32 (a uniform runtime flag, so the mixed kernel holds a
+// single copy of this loop for both phases) selects the FP32 pair arithmetic,
+// the Armijo noise allowance and the stall exit of the mixed path's first
+// phase.
+template <bool CAN32, int W, int A, bool HREG>
 __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][A],
                          double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
-                         const LbfgsDev& p, double gtol, int max_iter) {
+                         const LbfgsDev& p, double gtol, int max_iter, bool f32_flag) {
+    const bool F32 = CAN32 && f32_flag;
     double d[3][A], xt[3][A], gt[3][A];
     H.clear();
-    E = tm.template eval<F32>(x, g);
+    E = eval_phase<CAN32>(tm, x, g, F32);
     ++evals;
     double gg = tm.dot(g, g);  // later iterations get it from the curvature reduction
     int it = 0;
     int stall = 0;
+    int zone_wait = 0;
+    double zone_best = 1.0e300;
     const double ms2 = p.max_step * p.max_step;
     for (;;) {
         gnorm = sqrt(gg);
@@ -336,28 +354,30 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             // FP32 phase: a backtracked trial whose first-order decrease is
             // below the FP32 energy noise cannot be validated by the Armijo
             // test (noise could pass it), so the line search fails instead
-            if constexpr (F32) {
-                if (alpha < 1.0 && -(alpha * gd) < p.ls_noise * fabs(E)) break;
-            }
+            if (F32 && alpha < 1.0 && -(alpha * gd) < p.ls_noise * fabs(E)) break;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int a = 0; a < A; ++a) xt[c][a] = fma(alpha, d[c][a], x[c][a]);
-            Et = tm.template eval<F32>(xt, gt);
+            Et = eval_phase<CAN32>(tm, xt, gt, F32);
             ++evals;
             double rhs = fma(p.c1 * alpha, gd, E);
             // FP32 phase near its tolerance: the full quasi-Newton step may be
             // accepted within the FP32 energy noise; a backtracked step, or any
             // step farther from convergence, must show a real decrease
-            if constexpr (F32) {
-                if (alpha == 1.0 && noise_zone) rhs = rhs + p.ls_noise * fabs(E);
-            }
+            if (noise_zone && alpha == 1.0) rhs = rhs + p.ls_noise * fabs(E);
             if (Et <= rhs) {
                 ok = true;
                 break;
             }
             alpha = alpha * 0.5;
         }
+        // FP32 phase while atoms still overlap (E > 0): a step that lowers E
+        // by less than the FP32 resolution of E made no measurable progress
+        // (its direction was scaled down by the curvature of one extremely
+        // stiff pair) and counts as a failed line search, so the history is
+        // dropped for a steepest-descent restart
+        if (ok && F32 && E > 0.0 && !(E - Et > p.ls_noise * E)) ok = false;
         if (!ok) {
             if (uniform(H.hist) > 0) {
                 H.clear();
@@ -392,7 +412,15 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             return LJ_LSFAIL;
         }
         if (p.m > 0 && sy > p.curv_eps * sqrt(ss * yy)) H.push(d, g, 1.0 / sy, sy / yy, p.m);
-        if constexpr (F32) stall = (Et < E || !noise_zone) ? 0 : stall + 1;
+        stall = (Et < E || !noise_zone) ? 0 : stall + 1;
+        if (noise_zone) {
+            if (gnorm < 0.9 * zone_best) {
+                zone_best = gnorm;
+                zone_wait = 0;
+            } else {
+                ++zone_wait;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -403,11 +431,9 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
         E = Et;
         gg = ggt;
         ++it;
-        if constexpr (F32) {
-            if (stall >= 5) {
-                iters += it;
-                return kStall;
-            }
+        if (stall >= 5 || zone_wait >= kZonePatience) {  // FP32 phase's noise zone only
+            iters += it;
+            return kStall;
         }
     }
 }
@@ -416,7 +442,7 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
 // Persistent minimiser kernel: one launch per size class.
 // ---------------------------------------------------------------------------
 template <int MIXED, int W, int A, bool HREG>
-__global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
+__global__ __launch_bounds__(kWave* W, (HREG && W == 1) ? 2 : 1) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
@@ -454,11 +480,19 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                 x[c][a] = i < n ? args.xyz[c * total + o + i] : 0.0;
             }
         double E = 0.0, gn = 0.0;
-        int iters = 0, evals = 0, st;
-        if constexpr (MIXED) {
-            const double gtol32 = fmax(args.p.gtol, args.p.gtol_mixed_per_atom * (double)n);
-            const int r32 = lbfgs_run<true>(tm, H, x, g, E, gn, iters, evals, args.p, gtol32,
-                                            args.p.max_iter);
+        int iters = 0, evals = 0, st = LJ_CONVERGED;
+        // Mixed: phase 0 is the FP32 phase, phase 1 the FP64 polish from its
+        // end point (one call site, so one copy of the L-BFGS loop).
+        for (int phase = MIXED ? 0 : 1; phase < 2; ++phase) {
+            const bool f32 = phase == 0;
+            const double gt = f32 ? fmax(args.p.gtol, args.p.gtol_mixed_per_atom * (double)n)
+                                  : args.p.gtol;
+            const int r = lbfgs_run<MIXED != 0>(tm, H, x, g, E, gn, iters, evals, args.p, gt,
+                                                args.p.max_iter, f32);
+            if (!f32) {
+                st = r;
+                break;
+            }
             if (args.xyz_switch) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -468,10 +502,8 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                         if (i < n) args.xyz_switch[c * total + o + i] = x[c][a];
                     }
             }
-            if (args.p.polish) {
-                st = lbfgs_run<false>(tm, H, x, g, E, gn, iters, evals, args.p, args.p.gtol,
-                                      args.p.max_iter);
-            } else {
+            if (!args.p.polish) {
+                // report the FP32 end point re-evaluated in FP64
                 E = tm.template eval<false>(x, g);
                 ++evals;
                 const double gg = tm.dot(g, g);
@@ -480,14 +512,12 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                     st = LJ_NONFINITE;
                 else if (gn < args.p.gtol)
                     st = LJ_CONVERGED;
-                else if (r32 == LJ_CONVERGED || r32 == kStall || r32 == LJ_LSFAIL)
+                else if (r == LJ_CONVERGED || r == kStall || r == LJ_LSFAIL)
                     st = LJ_SWITCHED;  // the FP32 phase reached its tolerance or resolution
                 else
-                    st = r32 == LJ_NONFINITE ? LJ_LSFAIL : r32;
+                    st = r == LJ_NONFINITE ? LJ_LSFAIL : r;
+                break;
             }
-        } else {
-            st = lbfgs_run<false>(tm, H, x, g, E, gn, iters, evals, args.p, args.p.gtol,
-                                  args.p.max_iter);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
