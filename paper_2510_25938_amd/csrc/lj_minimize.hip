@@ -442,7 +442,7 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
 // Persistent minimiser kernel: one launch per size class.
 // ---------------------------------------------------------------------------
 template <int MIXED, int W, int A, bool HREG>
-__global__ __launch_bounds__(kWave* W, (HREG && W == 1) ? 2 : 1) void minimize_kernel(MinArgs args) {
+__global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
