@@ -67,6 +67,49 @@ struct Team {
         return team_max<W, A, NVMAX>(m, *sc, bank);
     }
 
+    // u.v and the largest per-atom squared norm of v, with the same values as
+    // dot() and max_atom_norm2() but one exchange between the wavefronts.
+    __device__ __forceinline__ void dot_max(const double (&u)[3][A], const double (&v)[3][A],
+                                            double& uv, double& vmax2) {
+        double p[A], m = 0.0;
+        double ws[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            p[a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
+            const double n2 = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
+            m = a == 0 ? n2 : fmax(m, n2);
+        }
+#pragma unroll
+        for (int a = 0; a < A; ++a) ws[a] = wave_sum(p[a]);
+        m = wave_max(m);
+        if constexpr (W == 1) {
+            uv = tree<A>(ws);
+            vmax2 = m;
+        } else {
+            const int w = threadIdx.x / kWave;
+            if (threadIdx.x % kWave == 0) {
+#pragma unroll
+                for (int a = 0; a < A; ++a) sc->v[bank][a][w] = ws[a];
+                sc->v[bank][A][w] = m;
+            }
+            __syncthreads();
+            double r[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+                double rw[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) rw[q] = sc->v[bank][a][q];
+                r[a] = tree<W>(rw);
+            }
+            double mx = sc->v[bank][A][0];
+#pragma unroll
+            for (int q = 1; q < W; ++q) mx = fmax(mx, sc->v[bank][A][q]);
+            bank ^= 1;
+            uv = uniform(tree<A>(r));
+            vmax2 = uniform(mx);
+        }
+    }
+
     // E and g at x.  F32: FP32 pair arithmetic and tile sums, FP64 totals.
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
@@ -139,9 +182,41 @@ struct History<W, A, true> {
         hist = hist < m ? hist + 1 : m;
     }
 
+    // r <- H r with all kMaxM pairs present: the same operations as apply(),
+    // with no per-pair guards (no branches or register copies between pairs).
+    __device__ __forceinline__ void apply_full(Team<W, A>& tm, double (&r)[3][A]) {
+        double al[kMaxM];
+#pragma unroll
+        for (int k = 0; k < kMaxM; ++k) {
+            const double a = rho[k] * tm.dot(S[k], r);
+            al[k] = a;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < A; ++q) r[c][q] = fma(-a, Y[k][c][q], r[c][q]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < A; ++q) r[c][q] = gamma * r[c][q];
+#pragma unroll
+        for (int k = kMaxM - 1; k >= 0; --k) {
+            const double b = rho[k] * tm.dot(Y[k], r);
+            const double w = al[k] - b;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < A; ++q) r[c][q] = fma(w, S[k][c][q], r[c][q]);
+        }
+    }
+
     // r <- H r (r holds g on entry).
     __device__ __forceinline__ void apply(Team<W, A>& tm, double (&r)[3][A]) {
         const int h = uniform(hist);
+        if (h == kMaxM) {
+            apply_full(tm, r);
+            return;
+        }
         double al[kMaxM];
 #pragma unroll
         for (int k = 0; k < kMaxM; ++k) {
@@ -299,13 +374,13 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
     E = eval_phase<CAN32>(tm, x, g, F32);
     ++evals;
     double gg = tm.dot(g, g);  // later iterations get it from the curvature reduction
+    gnorm = sqrt(gg);
     int it = 0;
     int stall = 0;
     int zone_wait = 0;
     double zone_best = 1.0e300;
     const double ms2 = p.max_step * p.max_step;
     for (;;) {
-        gnorm = sqrt(gg);
         if (!isfinite(E) || !isfinite(gg)) {
             iters += it;
             return LJ_NONFINITE;
@@ -328,16 +403,16 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int a = 0; a < A; ++a) d[c][a] = -d[c][a];
-        double gd = tm.dot(g, d);
+        double gd, dmax2;
+        tm.dot_max(g, d, gd, dmax2);
         if (uniform(H.hist) > 0 && !(gd < 0.0)) {
             H.clear();
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int a = 0; a < A; ++a) d[c][a] = -g[c][a];
-            gd = tm.dot(g, d);
+            tm.dot_max(g, d, gd, dmax2);
         }
-        const double dmax2 = tm.max_atom_norm2(d);
         if (dmax2 > ms2) {
             const double sc = p.max_step / sqrt(dmax2);
 #pragma unroll
@@ -411,7 +486,13 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             iters += it;
             return LJ_LSFAIL;
         }
-        if (p.m > 0 && sy > p.curv_eps * sqrt(ss * yy)) H.push(d, g, 1.0 / sy, sy / yy, p.m);
+        // the square roots and quotients of this step are independent of one
+        // another: formed together so their latencies overlap
+        const double gn_t = sqrt(ggt);
+        const double syy = sqrt(ss * yy);
+        const double rho_t = 1.0 / sy;
+        const double gam_t = sy / yy;
+        if (p.m > 0 && sy > p.curv_eps * syy) H.push(d, g, rho_t, gam_t, p.m);
         stall = (Et < E || !noise_zone) ? 0 : stall + 1;
         if (noise_zone) {
             if (gnorm < 0.9 * zone_best) {
@@ -430,6 +511,7 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
             }
         E = Et;
         gg = ggt;
+        gnorm = gn_t;
         ++it;
         if (stall >= 5 || zone_wait >= kZonePatience) {  // FP32 phase's noise zone only
             iters += it;
