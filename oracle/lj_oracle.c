@@ -80,6 +80,12 @@ double lj_o_tree_sum(const double* v, int64_t n) {
     return s;
 }
 
+double lj_o_exp_bh(double z);
+
+/* Pair potentials: Eq. (1) (reduced units) or the Morse pair.              */
+#define LJ_O_PAIR_LJ 0
+#define LJ_O_PAIR_MORSE 1
+
 /* ------------------------------------------------------------------------ */
 /* Eq. (1): E = 4 sum_{i<j} (r^-12 - r^-6) and its analytic gradient.       */
 /*                                                                          */
@@ -88,8 +94,8 @@ double lj_o_tree_sum(const double* v, int64_t n) {
 /* dE/dx_i = sum_{j != i} q s6 (24 - 48 s6) (x_i - x_j).                     */
 /* x, y, z point at the cluster's n coordinates; tmp has next_pow2(n) room. */
 /* ------------------------------------------------------------------------ */
-static double energy_grad(int n, const double* x, const double* y, const double* z,
-                          double* gx, double* gy, double* gz, double* tmp) {
+static double energy_grad_lj(int n, const double* x, const double* y, const double* z,
+                             double* gx, double* gy, double* gz, double* tmp) {
     for (int i = 0; i < n; ++i) {
         double e = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
         for (int j = 0; j < n; ++j) {
@@ -116,11 +122,59 @@ static double energy_grad(int n, const double* x, const double* y, const double*
     return 2.0 * tree_sum(tmp, n);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Morse pair (an empirical pair force field; the paper's conclusions name   */
+/* empirical force fields as the next potentials), in reduced units with    */
+/* well depth 1 at r = 1 and range rho:                                     */
+/*   V(r) = t (t - 2),  t = exp(rho (1 - r)),  dV/dr = -2 rho t (t - 1).    */
+/* Written per atom over ordered pairs: E = sum_{i<j} V = 0.5 sum_i e_i with */
+/* e_i = sum_{j != i} V(r_ij), and dE/dx_i = sum_{j != i} (dV/dr / r)        */
+/* (x_i - x_j).  r = IEEE sqrt(r^2); exp is exp_bh below (its reduction and  */
+/* polynomial hold for any z <= 709; here z <= rho).                        */
+/* ------------------------------------------------------------------------ */
+static double energy_grad_morse(int n, const double* x, const double* y, const double* z,
+                                double* gx, double* gy, double* gz, double* tmp, double rho) {
+    const double c = -2.0 * rho;
+    for (int i = 0; i < n; ++i) {
+        double e = 0.0, ax = 0.0, ay = 0.0, az = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j];
+            double dy = y[i] - y[j];
+            double dz = z[i] - z[j];
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double r = sqrt(r2);
+            double t = lj_o_exp_bh(fma(-rho, r, rho));
+            e = e + t * (t - 2.0);
+            double f = ((c * t) * (t - 1.0)) / r;
+            ax = fma(f, dx, ax);
+            ay = fma(f, dy, ay);
+            az = fma(f, dz, az);
+        }
+        tmp[i] = e;
+        if (gx) {
+            gx[i] = ax;
+            gy[i] = ay;
+            gz[i] = az;
+        }
+    }
+    return 0.5 * tree_sum(tmp, n);
+}
+
+static double energy_grad(int n, const double* x, const double* y, const double* z,
+                          double* gx, double* gy, double* gz, double* tmp, int pair,
+                          double rho) {
+    if (pair == LJ_O_PAIR_MORSE) return energy_grad_morse(n, x, y, z, gx, gy, gz, tmp, rho);
+    return energy_grad_lj(n, x, y, z, gx, gy, gz, tmp);
+}
+
 /* Sums of absolute pair terms, used by tests to bound the error of reduced
- * precision evaluations: eabs = 2 sum_i sum_{j!=i} (r^-12 + r^-6) and, per
- * atom and component, gabs = sum_{j!=i} |f_ij (x_i - x_j)|. */
+ * precision evaluations.  Eq. (1): eabs = 2 sum_i sum_{j!=i} (r^-12 + r^-6);
+ * Morse: eabs = 0.5 sum_i sum_{j!=i} (t^2 + 2 t).  Per atom and component,
+ * gabs = sum_{j!=i} |f_ij (x_i - x_j)|. */
 static void abs_sums(int n, const double* x, const double* y, const double* z,
-                     double* eabs, double* gax, double* gay, double* gaz) {
+                     double* eabs, double* gax, double* gay, double* gaz, int pair,
+                     double rho) {
     double tot = 0.0;
     for (int i = 0; i < n; ++i) {
         double ax = 0.0, ay = 0.0, az = 0.0;
@@ -128,10 +182,18 @@ static void abs_sums(int n, const double* x, const double* y, const double* z,
             if (j == i) continue;
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             double r2 = dx * dx + dy * dy + dz * dz;
-            double q = 1.0 / r2;
-            double s6 = q * q * q;
-            tot += s6 * s6 + s6;
-            double f = fabs(q * s6 * (24.0 + 48.0 * s6));
+            double f;
+            if (pair == LJ_O_PAIR_MORSE) {
+                double r = sqrt(r2);
+                double t = exp(rho * (1.0 - r));
+                tot += t * t + 2.0 * t;
+                f = 2.0 * rho * t * (t + 1.0) / r;
+            } else {
+                double q = 1.0 / r2;
+                double s6 = q * q * q;
+                tot += s6 * s6 + s6;
+                f = fabs(q * s6 * (24.0 + 48.0 * s6));
+            }
             ax += f * fabs(dx);
             ay += f * fabs(dy);
             az += f * fabs(dz);
@@ -140,13 +202,14 @@ static void abs_sums(int n, const double* x, const double* y, const double* z,
         gay[i] = ay;
         gaz[i] = az;
     }
-    *eabs = 2.0 * tot;
+    *eabs = (pair == LJ_O_PAIR_MORSE ? 0.5 : 2.0) * tot;
 }
 
 /* Batched entry: xyz is three planes [3][total] (x plane, y plane, z plane);
  * cluster b owns atoms offset[b] .. offset[b+1]-1.  grad may be NULL. */
 int lj_o_energy_grad_batch(int32_t num, const int32_t* offset, int64_t total,
-                           const double* xyz, double* energy, double* grad) {
+                           const double* xyz, double* energy, double* grad, int32_t pair,
+                           double rho) {
     int maxn = 0;
     for (int b = 0; b < num; ++b) {
         int n = offset[b + 1] - offset[b];
@@ -159,19 +222,19 @@ int lj_o_energy_grad_batch(int32_t num, const int32_t* offset, int64_t total,
         int n = offset[b + 1] - offset[b];
         energy[b] = energy_grad(n, xyz + o, xyz + total + o, xyz + 2 * total + o,
                                 grad ? grad + o : NULL, grad ? grad + total + o : NULL,
-                                grad ? grad + 2 * total + o : NULL, tmp);
+                                grad ? grad + 2 * total + o : NULL, tmp, pair, rho);
     }
     free(tmp);
     return 0;
 }
 
 int lj_o_abs_sums_batch(int32_t num, const int32_t* offset, int64_t total, const double* xyz,
-                        double* eabs, double* gabs) {
+                        double* eabs, double* gabs, int32_t pair, double rho) {
     for (int b = 0; b < num; ++b) {
         int64_t o = offset[b];
         int n = offset[b + 1] - offset[b];
         abs_sums(n, xyz + o, xyz + total + o, xyz + 2 * total + o, &eabs[b], gabs + o,
-                 gabs + total + o, gabs + 2 * total + o);
+                 gabs + total + o, gabs + 2 * total + o, pair, rho);
     }
     return 0;
 }
@@ -188,6 +251,8 @@ typedef struct {
     double c1;           /* Armijo constant                                 */
     int32_t max_ls;      /* backtracking halvings per line search           */
     double curv_eps;     /* store (s,y) only if s.y > curv_eps |s| |y|      */
+    int32_t pair;        /* LJ_O_PAIR_LJ (Eq. 1) or LJ_O_PAIR_MORSE         */
+    double rho;          /* Morse range                                     */
 } lj_o_lbfgs;
 
 /* A 3N-vector of one cluster is held as three planes of n doubles. */
@@ -214,8 +279,8 @@ static void vec_copy(int n, vec3n dst, vec3n src) {
     for (int k = 0; k < 3; ++k) memcpy(dst.c[k], src.c[k], (size_t)n * sizeof(double));
 }
 
-static double eval(int n, vec3n x, vec3n g, double* tmp) {
-    return energy_grad(n, x.c[0], x.c[1], x.c[2], g.c[0], g.c[1], g.c[2], tmp);
+static double eval(int n, vec3n x, vec3n g, double* tmp, const lj_o_lbfgs* p) {
+    return energy_grad(n, x.c[0], x.c[1], x.c[2], g.c[0], g.c[1], g.c[2], tmp, p->pair, p->rho);
 }
 
 /* Two-loop recursion (Nocedal & Wright, Alg. 7.4): r = H g, where H is the
@@ -307,7 +372,7 @@ static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, doub
     double gamma = 1.0;
     int32_t iters = 0, evals = 0;
     int status;
-    double E = eval(n, x, g, tmp);
+    double E = eval(n, x, g, tmp, p);
     ++evals;
     double gnorm = 0.0;
     const double ms2 = p->max_step * p->max_step;
@@ -359,7 +424,7 @@ static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, doub
         for (int ls = 0; ls < p->max_ls; ++ls) {
             for (int c = 0; c < 3; ++c)
                 for (int i = 0; i < n; ++i) xt.c[c][i] = fma(alpha, d.c[c][i], x.c[c][i]);
-            Et = eval(n, xt, gt, tmp);
+            Et = eval(n, xt, gt, tmp, p);
             ++evals;
             if (Et <= fma(p->c1 * alpha, gd, E)) {
                 ok = 1;
@@ -502,7 +567,8 @@ static uint64_t stream_word(uint64_t seed, uint64_t chain, uint64_t step, uint64
 /* z = k ln2 + r with ln2 split into a high part (low 32 bits zero) and a   */
 /* low part, then the Taylor series of e^r to degree 13 in Horner form      */
 /* (|r| <= ln2/2, truncation below 2^-53), then scaling by 2^k.  Returns 0  */
-/* for z < -708 or NaN; only z <= 0 is used.                                */
+/* for z < -708 or NaN.  The Metropolis test uses z <= 0; the Morse pair     */
+/* uses z <= rho (the reduction and polynomial hold up to z = 709).         */
 /* ------------------------------------------------------------------------ */
 double lj_o_exp_bh(double z) {
     if (!(z >= -708.0)) return 0.0;

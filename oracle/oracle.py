@@ -15,10 +15,13 @@ CONVERGED, MAXITER, LSFAIL, NONFINITE = 0, 1, 2, 3
 _lib = None
 
 
+PAIRS = {"lj": 0, "morse": 1}
+
+
 class LBFGSParams(C.Structure):
     _fields_ = [("m", C.c_int32), ("gtol", C.c_double), ("max_iter", C.c_int32),
                 ("max_step", C.c_double), ("c1", C.c_double), ("max_ls", C.c_int32),
-                ("curv_eps", C.c_double)]
+                ("curv_eps", C.c_double), ("pair", C.c_int32), ("rho", C.c_double)]
 
 
 class BHParams(C.Structure):
@@ -46,8 +49,8 @@ def lib():
         d, i32, i64, vp = C.c_double, C.c_int32, C.c_int64, C.c_void_p
         _lib.lj_o_tree_sum.restype = d
         _lib.lj_o_tree_sum.argtypes = [vp, i64]
-        _lib.lj_o_energy_grad_batch.argtypes = [i32, vp, i64, vp, vp, vp]
-        _lib.lj_o_abs_sums_batch.argtypes = [i32, vp, i64, vp, vp, vp]
+        _lib.lj_o_energy_grad_batch.argtypes = [i32, vp, i64, vp, vp, vp, i32, d]
+        _lib.lj_o_abs_sums_batch.argtypes = [i32, vp, i64, vp, vp, vp, i32, d]
         _lib.lj_o_minimize_batch.argtypes = [i32, vp, i64, vp, C.POINTER(LBFGSParams), vp, vp,
                                              vp, vp, vp]
         _lib.lj_o_two_loop.argtypes = [C.c_int, C.c_int, vp, vp, vp, d, vp, vp]
@@ -77,8 +80,8 @@ def _i32(a):
 
 
 def lbfgs_params(m=10, gtol=1e-6, max_iter=10000, max_step=0.2, c1=1e-4, max_ls=30,
-                 curv_eps=1e-10):
-    return LBFGSParams(m, gtol, max_iter, max_step, c1, max_ls, curv_eps)
+                 curv_eps=1e-10, pair="lj", rho=6.0):
+    return LBFGSParams(m, gtol, max_iter, max_step, c1, max_ls, curv_eps, PAIRS[pair], rho)
 
 
 def tree_sum(v):
@@ -86,22 +89,23 @@ def tree_sum(v):
     return lib().lj_o_tree_sum(_p(v), v.size)
 
 
-def energy_grad(offset, xyz):
-    """E[B] and gradient planes [3][T] of every cluster (Eq. 1 and its derivative)."""
+def energy_grad(offset, xyz, pair="lj", rho=6.0):
+    """E[B] and gradient planes [3][T] of every cluster (Eq. 1 and its
+    derivative, or the Morse pair of range rho)."""
     offset, xyz = _i32(offset), _f64(xyz)
     B, T = offset.size - 1, xyz.shape[-1]
     E = np.empty(B)
     g = np.empty((3, T))
-    lib().lj_o_energy_grad_batch(B, _p(offset), T, _p(xyz), _p(E), _p(g))
+    lib().lj_o_energy_grad_batch(B, _p(offset), T, _p(xyz), _p(E), _p(g), PAIRS[pair], rho)
     return E, g
 
 
-def abs_sums(offset, xyz):
+def abs_sums(offset, xyz, pair="lj", rho=6.0):
     offset, xyz = _i32(offset), _f64(xyz)
     B, T = offset.size - 1, xyz.shape[-1]
     eabs = np.empty(B)
     gabs = np.empty((3, T))
-    lib().lj_o_abs_sums_batch(B, _p(offset), T, _p(xyz), _p(eabs), _p(gabs))
+    lib().lj_o_abs_sums_batch(B, _p(offset), T, _p(xyz), _p(eabs), _p(gabs), PAIRS[pair], rho)
     return eabs, gabs
 
 
