@@ -142,6 +142,31 @@ def workloads(lj, inputs, torch, stream, oracle=None):
                            "median_iters": float(np.median(r["iters"].cpu().numpy()))}
         entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
         res[w.name] = entry
+    # the Morse pair (range 6) on the LJ38 batch shape: FP64 and mixed
+    w = inputs.morse38_batch()
+    off, x = w.starts()
+    b = lj.ClusterBatch(off, device=dev, pair=w.extra["pair"], rho=w.extra["rho"])
+    xd = torch.from_numpy(x).to(dev)
+    pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
+    entry = {"pair": "morse", "rho": w.extra["rho"]}
+    for prec in ("mixed", "fp64"):
+        ms, r = timed(torch, stream, lambda: lj.minimize(b, xd, lj.lbfgs_params(), prec,
+                                                         stream=stream))
+        st = r["status"].cpu().numpy()
+        ev = r["evals"].cpu().numpy().astype(np.int64)
+        entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
+                       "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
+                       "converged_frac": float(np.mean(st == lj.CONVERGED)),
+                       "median_iters": float(np.median(r["iters"].cpu().numpy())),
+                       "lowest_energy": float(r["energy"].min().item())}
+    entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
+    if oracle is not None:
+        sub = 64  # the oracle on the first 64 clusters of the batch
+        t0 = time.perf_counter()
+        oracle.minimize(off[:sub + 1], x[:, :off[sub]], oracle.lbfgs_params(pair="morse",
+                                                                            rho=w.extra["rho"]))
+        entry["cpu_oracle_minimisations_per_s"] = sub / (time.perf_counter() - t0)
+    res[w.name] = entry
     # many chains: 512 chains x 8 candidates, mixed (polish of accepted) and FP64
     w = inputs.many_chains()
     off, x = w.starts()

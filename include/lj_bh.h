@@ -76,18 +76,33 @@ typedef int32_t lj_status;
 #define LJ_MAX_M 10            /* largest L-BFGS history                          */
 #define LJ_MAX_CANDS 64        /* largest number of candidates per BH step        */
 
+/* Pair potential of a batch (lj_batch.pair).  LJ_PAIR_LJ is Eq. (1) in
+ * reduced units (sigma = epsilon = 1).  LJ_PAIR_MORSE is the Morse pair, an
+ * empirical pair force field of the kind the paper's conclusions name as the
+ * next potentials, in reduced units with well depth 1 at r = 1:
+ *   V(r) = t (t - 2),  t = exp(rho (1 - r)),  rho = lj_batch.pair_rho > 0
+ * (rho = 6 has the curvature of Eq. (1) at its minimum).  Other sigma and
+ * epsilon (or well depth and position) are host rescalings: E(x) =
+ * epsilon E_reduced(x / sigma), g = (epsilon / sigma) g_reduced. */
+#define LJ_PAIR_LJ 0
+#define LJ_PAIR_MORSE 1
+
 /* A ragged batch.  offset is a device pointer; the other fields are host
  * values that must agree with it: num = B >= 0, max_n >= every N_b,
- * total_atoms = offset[B]. */
+ * total_atoms = offset[B].  pair and pair_rho select the pair potential
+ * (zero-initialised: Eq. (1)). */
 typedef struct {
     int32_t num;
     const int32_t* offset;
     int32_t max_n;
     int64_t total_atoms;
+    int32_t pair;    /* LJ_PAIR_LJ or LJ_PAIR_MORSE                       */
+    double pair_rho; /* Morse range rho (finite, > 0); ignored for Eq. (1) */
 } lj_batch;
 
 /*
- * lj_energy_grad_batch - Eq. (1) and its analytic gradient for every cluster.
+ * lj_energy_grad_batch - Eq. (1) and its analytic gradient for every cluster
+ * (or the batch's Morse pair: E_b = sum_{i<j} V(r_ij)).
  *   E_b = 4 sum_{i<j} (r_ij^-12 - r_ij^-6),   g_i = dE/dx_i.
  * Paper: Methodology, "Lennard-Jones Potential", Eq. (1); the gradient is the
  * derivative of Eq. (1) that the L-BFGS-B minimiser consumes.
@@ -259,7 +274,7 @@ const char* lj_status_string(lj_status s);
 const char* lj_last_error(void);
 
 /* ABI version of this header (incremented on any incompatible change). */
-#define LJ_ABI_VERSION 1
+#define LJ_ABI_VERSION 2
 int32_t lj_abi_version(void);
 
 #ifdef __cplusplus

@@ -72,6 +72,11 @@ lj_status check_batch(const lj_batch* b, int limit, const char* what) {
                     (long long)b->total_atoms);
     if ((int64_t)b->num * b->max_n < b->total_atoms)
         return fail(LJ_E_ARG, "%s: total_atoms exceeds num * max_n", what);
+    if (b->pair != LJ_PAIR_LJ && b->pair != LJ_PAIR_MORSE)
+        return fail(LJ_E_ARG, "%s: pair = %d is neither LJ_PAIR_LJ nor LJ_PAIR_MORSE", what,
+                    b->pair);
+    if (b->pair == LJ_PAIR_MORSE && !(b->pair_rho > 0.0 && b->pair_rho <= 1.0e6))
+        return fail(LJ_E_ARG, "%s: Morse pair_rho = %g is not in (0, 1e6]", what, b->pair_rho);
     return LJ_OK;
 }
 
@@ -139,7 +144,7 @@ struct MinLayout {
     int grid[lj::kNumClasses] = {0, 0, 0, 0};
 };
 
-lj_status min_layout(int num, int max_n, int mixed, MinLayout& L, int large = -1) {
+lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int large = -1) {
     DeviceInfo di;
     lj_status s = device_info(di);
     if (s != LJ_OK) return s;
@@ -155,7 +160,7 @@ lj_status min_layout(int num, int max_n, int mixed, MinLayout& L, int large = -1
     auto grid_for = [&](int c, int large_shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, lj::minimize_kernel_for(mixed, c, large_shape),
+            &per_cu, lj::minimize_kernel_for(mixed, pot, c, large_shape),
             lj::class_block(c, large_shape), 0));
         if (per_cu < 1) per_cu = 1;
         long g = (long)per_cu * di.cus;
@@ -238,6 +243,8 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     a.xyz_switch = mixed ? xyz_switch : nullptr;
     a.plan = plan;
     a.p = p;
+    a.pot = b->pair;
+    a.rho = b->pair_rho;
     if (L.top_class == 0) {
         a.cls = 0;
         a.hist = nullptr;
@@ -294,9 +301,9 @@ lj_status bh_layout(const lj_batch* ch, const lj_bh_params* bh, int mixed, BhLay
     L.pi = take(sizeof(int32_t) * (size_t)ch->num);
     L.pv = take(sizeof(int32_t) * (size_t)ch->num);
     L.ps = take(sizeof(int32_t) * (size_t)ch->num);
-    lj_status s = min_layout(L.cand_num, ch->max_n, mixed, L.cand_min);
+    lj_status s = min_layout(L.cand_num, ch->max_n, mixed, ch->pair, L.cand_min);
     if (s != LJ_OK) return s;
-    s = min_layout(ch->num, ch->max_n, 0, L.polish_min);
+    s = min_layout(ch->num, ch->max_n, 0, ch->pair, L.polish_min);
     if (s != LJ_OK) return s;
     L.min = off;
     const size_t m = L.cand_min.total > L.polish_min.total ? L.cand_min.total : L.polish_min.total;
@@ -332,6 +339,8 @@ lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj:
     cb.offset = cand_off;
     cb.max_n = ch->max_n;
     cb.total_atoms = L.cand_total;
+    cb.pair = ch->pair;
+    cb.pair_rho = ch->pair_rho;
     lj::LbfgsDev d = to_dev(lp);
     if (mixed) d.polish = 0;  // only the accepted candidate is polished
     lj_status r = enqueue_minimize(&cb, nullptr, xc, ce, reinterpret_cast<double*>(ws + L.cg),
@@ -421,9 +430,10 @@ lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double*
     DeviceInfo di;
     s = device_info(di);
     if (s != LJ_OK) return s;
-    LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, eval_schedule(precision, batch->max_n),
-                                      batch->num, batch->offset, batch->total_atoms, xyz, energy,
-                                      grad, static_cast<hipStream_t>(stream)));
+    LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, batch->pair,
+                                      eval_schedule(precision, batch->max_n), batch->num,
+                                      batch->offset, batch->total_atoms, xyz, energy, grad,
+                                      batch->pair_rho, static_cast<hipStream_t>(stream)));
     return LJ_OK;
 }
 
@@ -432,7 +442,8 @@ size_t lj_minimize_workspace_bytes(const lj_batch* batch, const lj_lbfgs_params*
     (void)params;
     if (check_batch(batch, LJ_MAX_ATOMS_MIN, "lj_minimize_workspace_bytes") != LJ_OK) return 0;
     MinLayout L;
-    if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L) != LJ_OK) return 0;
+    if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, batch->pair, L) != LJ_OK)
+        return 0;
     return L.total;
 }
 
@@ -451,7 +462,7 @@ lj_status lj_bh_minimize_batch(const lj_batch* batch, double* xyz, double* energ
         return fail(LJ_E_ARG, "an output array is NULL");
     if (batch->total_atoms > 0 && !xyz) return fail(LJ_E_ARG, "xyz is NULL");
     MinLayout L;
-    if ((s = min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L)) != LJ_OK) return s;
+    if ((s = min_layout(batch->num, batch->max_n, precision == LJ_MIXED, batch->pair, L)) != LJ_OK) return s;
     if (!ws || ws_bytes < L.total)
         return fail(LJ_E_WORKSPACE, "workspace of %zu bytes given, %zu needed", ws_bytes, L.total);
     return enqueue_minimize(batch, nullptr, xyz, energy, gnorm, iters, evals, status, xyz_switch,
@@ -599,7 +610,8 @@ size_t lj_autotune_workspace_bytes(const lj_batch* batch, int32_t precision) {
         off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);  // xyz copy
         off = align_up(off + 5 * sizeof(double) * (size_t)batch->num);          // outputs
         MinLayout L;
-        if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, L) != LJ_OK) return 0;
+        if (min_layout(batch->num, batch->max_n, precision == LJ_MIXED, batch->pair, L) != LJ_OK)
+        return 0;
         off = align_up(off + L.total);
     }
     return off;
@@ -657,8 +669,9 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
             lj::EvalShape sh{wi, ai};
             float ms = 0.f;
             s = time_it([&]() -> lj_status {
-                LJ_HIP_TRY(lj::launch_energy_grad(mixed, sh, batch->num, batch->offset,
-                                                  batch->total_atoms, xyz, e, g, st));
+                LJ_HIP_TRY(lj::launch_energy_grad(mixed, batch->pair, sh, batch->num,
+                                                  batch->offset, batch->total_atoms, xyz, e, g,
+                                                  batch->pair_rho, st));
                 return LJ_OK;
             }, ms);
             if (s != LJ_OK) break;
@@ -690,7 +703,7 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
         best_min = 1e30f;
         for (int k = 0; k < lj::kNumLargeShapes && s == LJ_OK; ++k) {
             MinLayout L;
-            if ((s = min_layout(batch->num, batch->max_n, mixed, L, k)) != LJ_OK) break;
+            if ((s = min_layout(batch->num, batch->max_n, mixed, batch->pair, L, k)) != LJ_OK) break;
             float ms = 0.f;
             s = time_it([&]() -> lj_status {
                 LJ_HIP_TRY(hipMemcpyAsync(xc, xyz, sizeof(double) * 3 * (size_t)batch->total_atoms,

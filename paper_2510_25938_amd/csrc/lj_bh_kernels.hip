@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int cha
             } else {
                 const U64x4 r = philox4x64_10(0, (uint64_t)c, (uint64_t)k,
                                               kPurposeMetropolis << 32, p.seed, 0);
-                if (unit_double(r.v[0]) < exp_metropolis(-dE / p.kT)) acc = 1;
+                if (unit_double(r.v[0]) < exp_cw(-dE / p.kT)) acc = 1;
             }
             if (best < s.e_best_seen[c]) s.e_best_seen[c] = best;
             if (acc) {

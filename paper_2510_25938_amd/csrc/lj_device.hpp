@@ -1,6 +1,7 @@
 // Device building blocks for gfx950: team reductions in a fixed tree order,
-// the LDS-staged Lennard-Jones pair loops (FP64 and FP32), Philox4x64-10 and
-// the deterministic exp used by the Metropolis test.
+// the LDS-staged pair loops (Eq. (1) and the Morse pair, FP64 and FP32),
+// Philox4x64-10 and the deterministic exp of the Metropolis test and the
+// Morse pair.
 //
 // A "team" is the W wavefronts (64 lanes each) of one workgroup that work on
 // one cluster.  Atom i of a cluster lives in thread t = i mod T, slot
@@ -8,6 +9,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "lj_bh.h"
 
 namespace lj {
 
@@ -186,6 +189,36 @@ __device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<
 }
 
 // ---------------------------------------------------------------------------
+// exp(z) by Cody-Waite reduction z = k ln2 + r (ln2 split into a high part
+// with 32 trailing zero bits and a low part) and the degree-13 Taylor
+// polynomial of e^r in Horner form (|r| <= ln2/2, truncation error below
+// 2^-53), scaled by 2^k; 0 below -708 and for NaN.  Every operation is a
+// correctly rounded IEEE operation, so the result does not depend on the
+// device.  Used by the Metropolis test (z <= 0) and the Morse pair (z <= rho;
+// the reduction and polynomial hold up to z = 709).
+__device__ __forceinline__ double exp_cw(double z) {
+    if (!(z >= -708.0)) return 0.0;
+    const double kf = rint(z * 1.4426950408889634);
+    double r = fma(-kf, 6.93147180369123816490e-01, z);
+    r = fma(-kf, 1.90821492927058770002e-10, r);
+    double p = 1.0 / 6227020800.0;
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)kf);
+}
+
+// ---------------------------------------------------------------------------
 // Eq. (1) pair loops.  pos holds the cluster's coordinates in LDS as
 // (x, y, z, pad); every lane reads the same partner j (LDS broadcast).
 // Per atom i: e_i = sum_{j != i, ascending j} (s6^2 - s6) with q = 1/r^2,
@@ -225,6 +258,49 @@ __device__ __forceinline__ void pair_fp32(const float4 p, bool self, float xi, f
     gz = fmaf(f, dz, gz);
 }
 
+// Morse pair (reduced units: well depth 1 at r = 1, range rho):
+// V = t (t - 2), t = exp(rho (1 - r)); the gradient coefficient is
+// (dV/dr) / r = ((c t) (t - 1)) / r with c = -2 rho.  Per atom i the partner
+// sums are e_i = sum V and g_i = sum coefficient (x_i - x_j); E = 0.5 sum e_i.
+// The self pair contributes exactly zero.
+constexpr int kPairLJ = LJ_PAIR_LJ;
+constexpr int kPairMorse = LJ_PAIR_MORSE;
+
+__device__ __forceinline__ void pair_morse64(const double4 p, bool self, double xi, double yi,
+                                             double zi, double rho, double c, double& e,
+                                             double& gx, double& gy, double& gz) {
+    const double dx = xi - p.x;
+    const double dy = yi - p.y;
+    const double dz = zi - p.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double r = sqrt(r2);
+    const double t = self ? 0.0 : exp_cw(fma(-rho, r, rho));
+    e = e + t * (t - 2.0);
+    const double fn = (c * t) * (t - 1.0);
+    const double f = self ? 0.0 : fn / r;
+    gx = fma(f, dx, gx);
+    gy = fma(f, dy, gy);
+    gz = fma(f, dz, gz);
+}
+
+// FP32: hardware square root, base-2 exponential and reciprocal.
+__device__ __forceinline__ void pair_morse32(const float4 p, bool self, float xi, float yi,
+                                             float zi, float rho, float c, float& e, float& gx,
+                                             float& gy, float& gz) {
+    const float dx = xi - p.x;
+    const float dy = yi - p.y;
+    const float dz = zi - p.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float t = self ? 0.0f : __builtin_amdgcn_exp2f(fmaf(-rho, r, rho) * 1.44269504f);
+    const float q = self ? 0.0f : __builtin_amdgcn_rcpf(r);
+    e = e + t * (t - 2.0f);
+    const float f = ((c * t) * (t - 1.0f)) * q;
+    gx = fmaf(f, dx, gx);
+    gy = fmaf(f, dy, gy);
+    gz = fmaf(f, dz, gz);
+}
+
 // FP64: every operation rounded as written; partners are consumed in
 // ascending order, so each per-atom sum is reproducible.  Partner
 // coordinates are read from LDS in groups of kGroup64 ahead of the
@@ -232,11 +308,19 @@ __device__ __forceinline__ void pair_fp32(const float4 p, bool self, float xi, f
 constexpr int kGroup64 = 4;
 constexpr int kGroup32 = 8;
 
-template <int A, int T>
+template <int A, int T, int POT>
 __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ pos,
                                            const double (&x)[3][A], double (&e)[A],
-                                           double (&g)[3][A]) {
+                                           double (&g)[3][A], double rho) {
     const int t = threadIdx.x;
+    const double c = -2.0 * rho;
+    auto pair = [&](const double4 p, bool self, int a) {
+        if constexpr (POT == kPairMorse)
+            pair_morse64(p, self, x[0][a], x[1][a], x[2][a], rho, c, e[a], g[0][a], g[1][a],
+                         g[2][a]);
+        else
+            pair_fp64(p, self, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a], g[2][a]);
+    };
 #pragma unroll
     for (int a = 0; a < A; ++a) {
         e[a] = 0.0;
@@ -250,26 +334,23 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
 #pragma unroll
         for (int u = 0; u < kGroup64; ++u)
 #pragma unroll
-            for (int a = 0; a < A; ++a)
-                pair_fp64(p[u], j + u == a * T + t, x[0][a], x[1][a], x[2][a], e[a], g[0][a],
-                          g[1][a], g[2][a]);
+            for (int a = 0; a < A; ++a) pair(p[u], j + u == a * T + t, a);
     }
     for (; j < n; ++j) {
         const double4 p = pos[j];
 #pragma unroll
-        for (int a = 0; a < A; ++a)
-            pair_fp64(p, j == a * T + t, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a],
-                      g[2][a]);
+        for (int a = 0; a < A; ++a) pair(p, j == a * T + t, a);
     }
 }
 
 // FP32 pair arithmetic and FP32 accumulation over tiles of kTileJ partners;
 // each tile's per-atom partial sums are added into FP64 accumulators.
-template <int A, int T>
+template <int A, int T, int POT>
 __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ pos,
                                             const double (&x)[3][A], double (&e)[A],
-                                            double (&g)[3][A]) {
+                                            double (&g)[3][A], double rho) {
     const int t = threadIdx.x;
+    const float rf = (float)rho, cf = -2.0f * rf;
     float xf[3][A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -284,6 +365,14 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
         float te[A], tg[3][A];
 #pragma unroll
         for (int a = 0; a < A; ++a) te[a] = tg[0][a] = tg[1][a] = tg[2][a] = 0.0f;
+        auto pair = [&](const float4 p, bool self, int a) {
+            if constexpr (POT == kPairMorse)
+                pair_morse32(p, self, xf[0][a], xf[1][a], xf[2][a], rf, cf, te[a], tg[0][a],
+                             tg[1][a], tg[2][a]);
+            else
+                pair_fp32(p, self, xf[0][a], xf[1][a], xf[2][a], te[a], tg[0][a], tg[1][a],
+                          tg[2][a]);
+        };
         int j = j0;
         for (; j + kGroup32 <= j1; j += kGroup32) {
             float4 p[kGroup32];
@@ -292,16 +381,12 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 #pragma unroll
             for (int u = 0; u < kGroup32; ++u)
 #pragma unroll
-                for (int a = 0; a < A; ++a)
-                    pair_fp32(p[u], j + u == a * T + t, xf[0][a], xf[1][a], xf[2][a], te[a],
-                              tg[0][a], tg[1][a], tg[2][a]);
+                for (int a = 0; a < A; ++a) pair(p[u], j + u == a * T + t, a);
         }
         for (; j < j1; ++j) {
             const float4 p = pos[j];
 #pragma unroll
-            for (int a = 0; a < A; ++a)
-                pair_fp32(p, j == a * T + t, xf[0][a], xf[1][a], xf[2][a], te[a], tg[0][a],
-                          tg[1][a], tg[2][a]);
+            for (int a = 0; a < A; ++a) pair(p, j == a * T + t, a);
         }
 #pragma unroll
         for (int a = 0; a < A; ++a) {
@@ -352,34 +437,6 @@ constexpr uint64_t kPurposeMetropolis = 4;
 // Top 53 bits of a random word as a double in [0, 1).
 __device__ __forceinline__ double unit_double(uint64_t w) {
     return (double)(w >> 11) * 0x1.0p-53;
-}
-
-// exp(z) for z <= 0 by Cody-Waite reduction z = k ln2 + r (ln2 split into a
-// high part with 32 trailing zero bits and a low part) and the degree-13
-// Taylor polynomial of e^r in Horner form (|r| <= ln2/2, truncation error
-// below 2^-53), scaled by 2^k; 0 below -708 and for NaN.  Every operation is
-// a correctly rounded IEEE operation, so the result does not depend on the
-// device.
-__device__ __forceinline__ double exp_metropolis(double z) {
-    if (!(z >= -708.0)) return 0.0;
-    const double kf = rint(z * 1.4426950408889634);
-    double r = fma(-kf, 6.93147180369123816490e-01, z);
-    r = fma(-kf, 1.90821492927058770002e-10, r);
-    double p = 1.0 / 6227020800.0;
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return ldexp(p, (int)kf);
 }
 
 }  // namespace lj

@@ -48,6 +48,8 @@ struct MinArgs {
     int cls;
     double* hist;       // global history (class 3): per persistent workgroup
     LbfgsDev p;
+    int pot;            // LJ_PAIR_LJ or LJ_PAIR_MORSE
+    double rho;         // Morse range
 };
 
 // Launchers (lj_minimize.hip, lj_bh_kernels.hip).
@@ -57,12 +59,13 @@ struct EvalShape {
 constexpr int kNumLargeShapes = 3;  // minimiser shapes for N in 257..1024
 EvalShape eval_shape(int max_n);
 bool eval_shape_supported(EvalShape s);
-hipError_t launch_energy_grad(int mixed, EvalShape s, int num, const int32_t* off, int64_t total,
-                              const double* xyz, double* e, double* g, hipStream_t st);
+hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const int32_t* off,
+                              int64_t total, const double* xyz, double* e, double* g, double rho,
+                              hipStream_t st);
 int class_of(int n);
 int class_block(int c, int large);
 size_t class_hist_bytes_per_wg(int c, int large);
-const void* minimize_kernel_for(int mixed, int c, int large);
+const void* minimize_kernel_for(int mixed, int pot, int c, int large);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);
 hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,

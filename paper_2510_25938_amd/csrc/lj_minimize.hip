@@ -20,7 +20,7 @@ namespace lj {
 // ---------------------------------------------------------------------------
 // Team: LDS buffers and the collective operations of one workgroup.
 // ---------------------------------------------------------------------------
-template <int W, int A>
+template <int W, int A, int POT>
 struct Team {
     static constexpr int T = kWave * W;
     static constexpr int NVMAX = 4 * A;
@@ -29,6 +29,7 @@ struct Team {
     TeamScratch<W, NVMAX>* sc;
     int bank;
     int n;
+    double rho;  // Morse range (POT == kPairMorse)
 
     __device__ __forceinline__ bool active(int a) const { return a * T + (int)threadIdx.x < n; }
 
@@ -111,6 +112,9 @@ struct Team {
     }
 
     // E and g at x.  F32: FP32 pair arithmetic and tile sums, FP64 totals.
+    // Ordered pairs count each pair twice: E = 2 sum_i e_i for Eq. (1)
+    // (e_i holds r^-12 - r^-6, a quarter of the pair energy) and
+    // E = 0.5 sum_i e_i for the Morse pair (e_i holds V).
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
         __syncthreads();  // previous readers of the position buffer are done
@@ -127,14 +131,14 @@ struct Team {
         __syncthreads();
         double e[1][A], o[1];
         if constexpr (F32)
-            pairs_mixed<A, T>(n, pos32, x, e[0], g);
+            pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
         else
-            pairs_fp64<A, T>(n, pos64, x, e[0], g);
+            pairs_fp64<A, T, POT>(n, pos64, x, e[0], g, rho);
 #pragma unroll
         for (int a = 0; a < A; ++a)
             if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
         team_sum<W, A, 1, NVMAX>(e, o, *sc, bank);
-        return 2.0 * o[0];
+        return (POT == kPairMorse ? 0.5 : 2.0) * o[0];
     }
 };
 
@@ -184,7 +188,8 @@ struct History<W, A, true> {
 
     // r <- H r with all kMaxM pairs present: the same operations as apply(),
     // with no per-pair guards (no branches or register copies between pairs).
-    __device__ __forceinline__ void apply_full(Team<W, A>& tm, double (&r)[3][A]) {
+    template <class TM>
+    __device__ __forceinline__ void apply_full(TM& tm, double (&r)[3][A]) {
         double al[kMaxM];
 #pragma unroll
         for (int k = 0; k < kMaxM; ++k) {
@@ -211,7 +216,8 @@ struct History<W, A, true> {
     }
 
     // r <- H r (r holds g on entry).
-    __device__ __forceinline__ void apply(Team<W, A>& tm, double (&r)[3][A]) {
+    template <class TM>
+    __device__ __forceinline__ void apply(TM& tm, double (&r)[3][A]) {
         const int h = uniform(hist);
         if (h == kMaxM) {
             apply_full(tm, r);
@@ -290,7 +296,8 @@ struct History<W, A, false> {
         hist = hist < mm ? hist + 1 : mm;
     }
 
-    __device__ __forceinline__ void apply(Team<W, A>& tm, double (&r)[3][A]) {
+    template <class TM>
+    __device__ __forceinline__ void apply(TM& tm, double (&r)[3][A]) {
         const int h = uniform(hist);
         double al[kMaxM];
         double v[3][A];
@@ -350,8 +357,8 @@ constexpr double kNoiseZone = 100.0;
 constexpr int kZonePatience = 30;
 
 // E and g at x with FP32 pair arithmetic when f32 (only compiled when CAN32).
-template <bool CAN32, int W, int A>
-__device__ __forceinline__ double eval_phase(Team<W, A>& tm, const double (&x)[3][A],
+template <bool CAN32, int W, int A, int POT>
+__device__ __forceinline__ double eval_phase(Team<W, A, POT>& tm, const double (&x)[3][A],
                                              double (&g)[3][A], bool f32) {
     if constexpr (CAN32) {
         if (f32) return tm.template eval<true>(x, g);
@@ -364,8 +371,8 @@ __device__ __forceinline__ double eval_phase(Team<W, A>& tm, const double (&x)[3
 // single copy of this loop for both phases) selects the FP32 pair arithmetic,
 // the Armijo noise allowance and the stall exit of the mixed path's first
 // phase.
-template <bool CAN32, int W, int A, bool HREG>
-__device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][A],
+template <bool CAN32, int W, int A, bool HREG, int POT>
+__device__ int lbfgs_run(Team<W, A, POT>& tm, History<W, A, HREG>& H, double (&x)[3][A],
                          double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
                          const LbfgsDev& p, double gtol, int max_iter, bool f32_flag) {
     const bool F32 = CAN32 && f32_flag;
@@ -523,18 +530,19 @@ __device__ int lbfgs_run(Team<W, A>& tm, History<W, A, HREG>& H, double (&x)[3][
 // ---------------------------------------------------------------------------
 // Persistent minimiser kernel: one launch per size class.
 // ---------------------------------------------------------------------------
-template <int MIXED, int W, int A, bool HREG>
+template <int MIXED, int W, int A, bool HREG, int POT>
 __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
     __shared__ int claim;
 
-    Team<W, A> tm;
+    Team<W, A, POT> tm;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
     tm.sc = &scratch;
     tm.bank = 0;
+    tm.rho = args.rho;
     History<W, A, HREG> H;
     constexpr size_t kHistPerWG = (size_t)2 * kMaxM * 3 * A * T;
     H.init(args.hist ? args.hist + kHistPerWG * blockIdx.x : nullptr, args.p.m);
@@ -672,10 +680,10 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* offset, int n
 // ---------------------------------------------------------------------------
 // Batched energy + gradient: one workgroup per cluster.
 // ---------------------------------------------------------------------------
-template <int MIXED, int W, int A>
+template <int MIXED, int W, int A, int POT>
 __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* offset, int64_t total,
                                                                const double* xyz, double* energy,
-                                                               double* grad) {
+                                                               double* grad, double rho) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
@@ -686,12 +694,13 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
         if (threadIdx.x == 0) energy[b] = __builtin_nan("");
         return;
     }
-    Team<W, A> tm;
+    Team<W, A, POT> tm;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
     tm.sc = &scratch;
     tm.bank = 0;
     tm.n = n;
+    tm.rho = rho;
     double x[3][A], g[3][A];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -733,15 +742,16 @@ bool eval_shape_supported(EvalShape s) {
     return w && a;
 }
 
-template <int MIXED>
+template <int MIXED, int POT>
 static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_t total,
-                                const double* xyz, double* e, double* g, hipStream_t st) {
+                                const double* xyz, double* e, double* g, double rho,
+                                hipStream_t st) {
     dim3 grid(num), block(kWave * s.W);
-#define LJ_EVAL_CASE(WW, AA)                                                                   \
-    if (s.W == WW && s.A == AA) {                                                              \
-        hipLaunchKernelGGL((energy_grad_kernel<MIXED, WW, AA>), grid, block, 0, st, off, total, \
-                           xyz, e, g);                                                         \
-        return hipGetLastError();                                                              \
+#define LJ_EVAL_CASE(WW, AA)                                                                  \
+    if (s.W == WW && s.A == AA) {                                                             \
+        hipLaunchKernelGGL((energy_grad_kernel<MIXED, WW, AA, POT>), grid, block, 0, st, off, \
+                           total, xyz, e, g, rho);                                            \
+        return hipGetLastError();                                                             \
     }
     LJ_EVAL_CASE(1, 1)
     LJ_EVAL_CASE(2, 1)
@@ -762,10 +772,14 @@ static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_energy_grad(int mixed, EvalShape s, int num, const int32_t* off, int64_t total,
-                              const double* xyz, double* e, double* g, hipStream_t st) {
-    return mixed ? launch_eval_t<1>(s, num, off, total, xyz, e, g, st)
-                 : launch_eval_t<0>(s, num, off, total, xyz, e, g, st);
+hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const int32_t* off,
+                              int64_t total, const double* xyz, double* e, double* g, double rho,
+                              hipStream_t st) {
+    if (pot == kPairMorse)
+        return mixed ? launch_eval_t<1, kPairMorse>(s, num, off, total, xyz, e, g, rho, st)
+                     : launch_eval_t<0, kPairMorse>(s, num, off, total, xyz, e, g, rho, st);
+    return mixed ? launch_eval_t<1, kPairLJ>(s, num, off, total, xyz, e, g, rho, st)
+                 : launch_eval_t<0, kPairLJ>(s, num, off, total, xyz, e, g, rho, st);
 }
 
 // Minimiser shapes.  Classes 0-2 keep the history in registers (one, two,
@@ -795,32 +809,38 @@ size_t class_hist_bytes_per_wg(int c, int large) {
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
-template <int MIXED, int W, int A, bool HREG>
+template <int MIXED, int W, int A, bool HREG, int POT>
 static const void* min_kernel_ptr() {
-    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG>);
+    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT>);
 }
 
-const void* minimize_kernel_for(int mixed, int c, int large) {
+template <int POT>
+static const void* minimize_kernel_pot(int mixed, int c, int large) {
     if (c < 3) {
         switch (c * 2 + (mixed ? 1 : 0)) {
-            case 0: return min_kernel_ptr<0, 1, 1, true>();
-            case 1: return min_kernel_ptr<1, 1, 1, true>();
-            case 2: return min_kernel_ptr<0, 2, 1, true>();
-            case 3: return min_kernel_ptr<1, 2, 1, true>();
-            case 4: return min_kernel_ptr<0, 4, 1, true>();
-            case 5: return min_kernel_ptr<1, 4, 1, true>();
+            case 0: return min_kernel_ptr<0, 1, 1, true, POT>();
+            case 1: return min_kernel_ptr<1, 1, 1, true, POT>();
+            case 2: return min_kernel_ptr<0, 2, 1, true, POT>();
+            case 3: return min_kernel_ptr<1, 2, 1, true, POT>();
+            case 4: return min_kernel_ptr<0, 4, 1, true, POT>();
+            case 5: return min_kernel_ptr<1, 4, 1, true, POT>();
         }
         return nullptr;
     }
     switch (large * 2 + (mixed ? 1 : 0)) {
-        case 0: return min_kernel_ptr<0, 16, 1, false>();
-        case 1: return min_kernel_ptr<1, 16, 1, false>();
-        case 2: return min_kernel_ptr<0, 8, 2, false>();
-        case 3: return min_kernel_ptr<1, 8, 2, false>();
-        case 4: return min_kernel_ptr<0, 4, 4, false>();
-        case 5: return min_kernel_ptr<1, 4, 4, false>();
+        case 0: return min_kernel_ptr<0, 16, 1, false, POT>();
+        case 1: return min_kernel_ptr<1, 16, 1, false, POT>();
+        case 2: return min_kernel_ptr<0, 8, 2, false, POT>();
+        case 3: return min_kernel_ptr<1, 8, 2, false, POT>();
+        case 4: return min_kernel_ptr<0, 4, 4, false, POT>();
+        case 5: return min_kernel_ptr<1, 4, 4, false, POT>();
     }
     return nullptr;
+}
+
+const void* minimize_kernel_for(int mixed, int pot, int c, int large) {
+    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large)
+                             : minimize_kernel_pot<kPairLJ>(mixed, c, large);
 }
 
 int class_block(int c, int large) { return kWave * shape_of(c, large).W; }
@@ -834,7 +854,7 @@ hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t*
 
 hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,
                                  hipStream_t st) {
-    const void* k = minimize_kernel_for(mixed, c, large);
+    const void* k = minimize_kernel_for(mixed, a.pot, c, large);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {const_cast<MinArgs*>(&a)};
     return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large)), args, 0, st);

@@ -110,3 +110,10 @@ def many_chains(chains: int = 512, lo: int = 38, hi: int = 75, steps: int = 1000
     seed = SEED_BASE + 5
     return Workload(f"chains-{chains}x8x{steps}-{lo}-{hi}", uniform_sizes(chains, lo, hi, seed),
                     seed, "mixed", chains=chains, cands=8, steps=steps)
+
+
+def morse38_batch(count: int = 1024, rho: float = 6.0) -> Workload:
+    """1024 independent 38-atom Morse clusters (range rho) from random cube
+    starts, one launch: the LJ38 batch with the Morse pair."""
+    return Workload(f"morse38-rho{rho:g}-batch-{count}", np.full(count, 38), SEED_BASE + 6,
+                    "mixed", extra={"pair": "morse", "rho": rho})

@@ -25,9 +25,12 @@ EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_
             "lj_last_error", "lj_abi_version"]
 
 
+PAIRS = {"lj": 0, "morse": 1}  # LJ_PAIR_LJ (Eq. 1), LJ_PAIR_MORSE
+
+
 class Batch(C.Structure):
     _fields_ = [("num", C.c_int32), ("offset", C.c_void_p), ("max_n", C.c_int32),
-                ("total_atoms", C.c_int64)]
+                ("total_atoms", C.c_int64), ("pair", C.c_int32), ("pair_rho", C.c_double)]
 
 
 class LbfgsParams(C.Structure):
@@ -135,9 +138,14 @@ def lbfgs_params(**kw):
 
 
 class ClusterBatch:
-    """A ragged batch: host sizes plus the device int32 prefix-sum offsets."""
+    """A ragged batch: host sizes plus the device int32 prefix-sum offsets, and
+    the pair potential ("lj": Eq. (1); "morse": the Morse pair of range rho,
+    well depth 1 at r = 1), both in reduced units."""
 
-    def __init__(self, offset, device="cuda"):
+    def __init__(self, offset, device="cuda", pair="lj", rho=6.0):
+        if pair not in PAIRS:
+            raise ValueError(f"pair must be one of {sorted(PAIRS)}")
+        self.pair, self.rho = pair, float(rho)
         off = np.asarray(offset, dtype=np.int64)
         if off.ndim != 1 or off.size < 1 or off[0] != 0 or np.any(np.diff(off) < 0):
             raise ValueError("offset must be nondecreasing prefix sums starting at 0")
@@ -150,12 +158,31 @@ class ClusterBatch:
 
     def desc(self, max_n=None):
         return Batch(self.num, self.offset.data_ptr(), self.max_n if max_n is None else max_n,
-                     self.total)
+                     self.total, PAIRS[self.pair], self.rho)
 
 
-def energy_grad(batch, xyz, precision="fp64", grad=True, stream=None):
-    """Eq. (1) energies [num] and gradient planes [3][total] (None if grad=False)."""
+# Units.  The kernels work in reduced units (sigma = epsilon = 1 for Eq. (1);
+# well position and depth 1 for the Morse pair).  Other length and energy
+# units are a conversion of the inputs and outputs: E(x) = epsilon
+# E_reduced(x / sigma), g(x) = (epsilon / sigma) g_reduced(x / sigma).
+def to_reduced(xyz, sigma=1.0):
+    return xyz if sigma == 1.0 else (xyz / sigma).contiguous()
+
+
+def from_reduced(energy=None, grad=None, xyz=None, sigma=1.0, epsilon=1.0):
+    return (None if energy is None else energy * epsilon,
+            None if grad is None else grad * (epsilon / sigma),
+            None if xyz is None else xyz * sigma)
+
+
+def energy_grad(batch, xyz, precision="fp64", grad=True, stream=None, sigma=1.0, epsilon=1.0):
+    """Energies [num] and gradient planes [3][total] (None if grad=False) of the
+    batch's pair potential; sigma / epsilon convert from other units."""
     assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
+    if sigma != 1.0 or epsilon != 1.0:
+        E, g = energy_grad(batch, to_reduced(xyz, sigma), precision, grad, stream)
+        E, g, _ = from_reduced(E, g, sigma=sigma, epsilon=epsilon)
+        return E, g
     E = torch.empty(batch.num, dtype=torch.float64, device=xyz.device)
     g = torch.empty_like(xyz) if grad else None
     _check(lib().lj_energy_grad_batch(C.byref(batch.desc()), _ptr(xyz), _ptr(E), _ptr(g),
@@ -170,10 +197,24 @@ def minimize_workspace_bytes(batch, params=None, precision="fp64"):
 
 
 def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, workspace=None,
-             stream=None, inplace=False):
-    """Local minimisation of every cluster; returns a dict of device tensors."""
+             stream=None, inplace=False, sigma=1.0, epsilon=1.0):
+    """Local minimisation of every cluster; returns a dict of device tensors.
+    params are in reduced units; sigma / epsilon convert the coordinates in and
+    the coordinates, energies and gradient norms out."""
     params = params or lbfgs_params()
     assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
+    if sigma != 1.0 or epsilon != 1.0:
+        out = minimize(batch, to_reduced(xyz, sigma), params, precision, switch_point, workspace,
+                       stream, inplace=True)
+        out["energy"], _, out["xyz"] = from_reduced(out["energy"], xyz=out["xyz"], sigma=sigma,
+                                                    epsilon=epsilon)
+        out["gnorm"] = out["gnorm"] * (epsilon / sigma)
+        if out["xyz_switch"] is not None:
+            out["xyz_switch"] = out["xyz_switch"] * sigma
+        if inplace:
+            xyz.copy_(out["xyz"])
+            out["xyz"] = xyz
+        return out
     dev = xyz.device
     x = xyz if inplace else xyz.clone()
     out = dict(xyz=x, energy=torch.empty(batch.num, dtype=torch.float64, device=dev),

@@ -29,10 +29,25 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     L = lj.lib()
-    assert L.lj_abi_version() == 1
+    assert L.lj_abi_version() == 2
     assert L.lj_status_string(lj.OK) == b"LJ_OK"
     for s in (lj.E_ARG, lj.E_HIP, lj.E_WORKSPACE, lj.E_UNSUPPORTED):
         assert L.lj_status_string(s).startswith(b"LJ_E_")
+
+
+def test_pair_selection_is_validated_on_the_host():
+    L = lj.lib()
+    assert C.sizeof(lj.Batch) == 48  # int32, ptr, int32, int64, int32, double (natural alignment)
+    for pair, rho in ((2, 6.0), (-1, 6.0), (lj.PAIRS["morse"], 0.0), (lj.PAIRS["morse"], -3.0),
+                      (lj.PAIRS["morse"], float("nan")), (lj.PAIRS["morse"], float("inf"))):
+        b = lj.Batch(2, 16, 13, 26, pair, rho)
+        assert L.lj_energy_grad_batch(C.byref(b), 16, 16, None, lj.FP64, None) == lj.E_ARG
+        assert b"pair" in L.lj_last_error()
+        p = lj.lbfgs_params()
+        assert (L.lj_bh_minimize_batch(C.byref(b), None, None, None, None, None, None, None,
+                                       C.byref(p), lj.FP64, None, 0, None) == lj.E_ARG)
+    with pytest.raises(ValueError):
+        lj.ClusterBatch([0, 3], device="cpu", pair="buckingham")
 
 
 def test_defaults():
