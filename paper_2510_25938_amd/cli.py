@@ -2,6 +2,7 @@
 
     python -m paper_2510_25938_amd.cli input.molden [--steps 200] [--cands 8]
         [--kT 1.0] [--step0 0.4] [--precision fp64|mixed] [--seed S]
+        [--pair lj|morse] [--rho 6.0] [--sigma 1.0]
 
 Reads the first geometry of input.molden (Methodology, "Initial Structures
 and Input"), minimises it, runs the basin-hopping loop of the Algorithm
@@ -30,6 +31,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=2510)
     ap.add_argument("--sigma", type=float, default=1.0,
                     help="length unit of the file in LJ sigma (coordinates are divided by it)")
+    ap.add_argument("--pair", default="lj", choices=["lj", "morse"],
+                    help="pair potential: Eq. (1) or the Morse pair (well depth 1 at r = 1)")
+    ap.add_argument("--rho", type=float, default=6.0, help="Morse range")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args(argv)
 
@@ -42,7 +46,7 @@ def main(argv=None):
     flat, syms = read_first_geometry(args.molden)
     n = len(syms)
     x = aos_to_planes(flat / args.sigma)
-    batch = lj.ClusterBatch(np.array([0, n], np.int32))
+    batch = lj.ClusterBatch(np.array([0, n], np.int32), pair=args.pair, rho=args.rho)
     xd = torch.from_numpy(x).to("cuda")
     params = lj.lbfgs_params()
     r = lj.minimize(batch, xd, params, "fp64")
