@@ -399,6 +399,139 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 }
 
 // ---------------------------------------------------------------------------
+// FP32 Eq. (1) over unique pairs for large clusters: 64-atom tiles, one per
+// wavefront-lane set (tile tau = atoms 64 tau .. 64 tau + 63, owned by the
+// thread that holds them: tau = a W + w).  The tile's coordinates are staged
+// twice in LDS (pos[128 tau + l] = pos[128 tau + 64 + l] = atom 64 tau + l),
+// so lane l reaches atom (l + k) mod 64 of a tile at an immediate offset.
+//   - diagonal: lane l pairs with l + 1 .. l + 63 of its own tile (every pair
+//     of the tile twice, no reaction);
+//   - round t = 1 .. nt/2: tile tau pairs with tile J = tau + t (mod nt), every
+//     pair once; for even nt the last round runs on tau < nt/2 only.  The
+//     reaction on J's atom (l + k) accumulates in a register that is rotated
+//     one lane per step (DPP wave_rol:1, folded into the add) so that after
+//     64 steps lane l holds the reaction on J's atom l; it goes to the LDS
+//     buffer of the round, and after the round's barrier the owner of J adds
+//     it.  In a round every tile is the partner of at most one tile, so no
+//     two writers meet (no atomics) and all sums have a fixed order.
+// Atoms n .. 64 nt - 1 are padding placed 1e8 apart on the x axis: their
+// pair terms underflow to exactly zero.  FP32 partial sums cover one tile
+// pair (at most 64 terms) and are added into FP64.  e_i is returned in the
+// ordered-pair convention of pairs_mixed (E = 2 sum e_i): a unique pair adds
+// twice its term to the lane that evaluates it.
+// ---------------------------------------------------------------------------
+template <int W, int A>
+constexpr bool kUseTiles = W * A * kWave >= 512 && W * A * kWave <= 2048;
+
+constexpr float kPadSpacing = 1.0e8f;
+
+__device__ __forceinline__ float rol1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float4 tile_pad(int i) {
+    return make_float4(kPadSpacing * (float)(1 + (i & 63)), 0.0f, 0.0f, 0.0f);
+}
+
+// Unique pairs of tile (pi: this lane's atom) with tile pj (base: partner
+// tile's doubled copy); returns the reaction on partner atom `lane`.
+__device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __restrict__ base,
+                                            int lane, float& te, float& tx, float& ty, float& tz) {
+    float rx = 0.0f, ry = 0.0f, rz = 0.0f;
+    const float4* src = base + lane;
+#pragma unroll 1
+    for (int k0 = 0; k0 < kWave; k0 += kGroup32) {
+        float4 p[kGroup32];
+#pragma unroll
+        for (int u = 0; u < kGroup32; ++u) p[u] = src[k0 + u];
+#pragma unroll
+        for (int u = 0; u < kGroup32; ++u) {
+            const float dx = pi.x - p[u].x;
+            const float dy = pi.y - p[u].y;
+            const float dz = pi.z - p[u].z;
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float q = __builtin_amdgcn_rcpf(r2);
+            const float s6 = (q * q) * q;
+            te = te + fmaf(s6, s6, -s6);
+            const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+            tx = fmaf(f, dx, tx);
+            ty = fmaf(f, dy, ty);
+            tz = fmaf(f, dz, tz);
+            // lane l's accumulator moves to lane l - 1 before each step, so it
+            // follows partner atom l + k (at k = 0 it rotates zeros)
+            rx = rol1(rx) - f * dx;
+            ry = rol1(ry) - f * dy;
+            rz = rol1(rz) - f * dz;
+        }
+    }
+    return make_float3(rol1(rx), rol1(ry), rol1(rz));
+}
+
+template <int W, int A>
+__device__ __forceinline__ void pairs_tiles(int n, const float4* __restrict__ pos,
+                                            float* __restrict__ rbuf, double (&e)[A],
+                                            double (&g)[3][A]) {
+    constexpr int T = kWave * W;
+    constexpr int S = T * A;  // plane stride of the reaction buffer
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    const int nt = (n + kWave - 1) / kWave;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+        e[a] = 0.0;
+        g[0][a] = g[1][a] = g[2][a] = 0.0;
+        const int tau = a * W + w;
+        if (tau >= nt) continue;
+        const float4 pi = pos[128 * tau + lane];
+        const float4* src = pos + 128 * tau + lane;
+        float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
+#pragma unroll 1
+        for (int k0 = 1; k0 < kWave; k0 += 9) {  // 63 partners in 7 groups of 9
+            float4 p[9];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) p[u] = src[k0 + u];
+#pragma unroll
+            for (int u = 0; u < 9; ++u)
+                pair_fp32(p[u], false, pi.x, pi.y, pi.z, te, tx, ty, tz);
+        }
+        e[a] += (double)te;
+        g[0][a] += (double)tx;
+        g[1][a] += (double)ty;
+        g[2][a] += (double)tz;
+    }
+    const int rounds = nt / 2;
+    for (int t = 1; t <= rounds; ++t) {
+        const bool half = (nt % 2 == 0) && t == rounds;
+        float* rb = rbuf + (t & 1) * 3 * S;
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int tau = a * W + w;
+            if (tau >= nt || (half && tau >= rounds)) continue;
+            int J = tau + t;
+            if (J >= nt) J -= nt;
+            const float4 pi = pos[128 * tau + lane];
+            float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
+            const float3 r = tile_pair(pi, pos + 128 * J, lane, te, tx, ty, tz);
+            e[a] += 2.0 * (double)te;
+            g[0][a] += (double)tx;
+            g[1][a] += (double)ty;
+            g[2][a] += (double)tz;
+            rb[64 * J + lane] = r.x;
+            rb[S + 64 * J + lane] = r.y;
+            rb[2 * S + 64 * J + lane] = r.z;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int tau = a * W + w;
+            if (tau >= nt || (half && tau < rounds)) continue;  // no partner wrote to tau
+            g[0][a] += (double)rb[64 * tau + lane];
+            g[1][a] += (double)rb[S + 64 * tau + lane];
+            g[2][a] += (double)rb[2 * S + 64 * tau + lane];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 64x64->128-bit multiplies; the key is bumped by the Weyl constants between
 // rounds.

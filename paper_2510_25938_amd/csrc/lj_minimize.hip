@@ -26,6 +26,7 @@ struct Team {
     static constexpr int NVMAX = 4 * A;
     double4* pos64;
     float4* pos32;
+    float* rbuf;  // reaction buffers of the tiled FP32 loop (kUseTiles teams)
     TeamScratch<W, NVMAX>* sc;
     int bank;
     int n;
@@ -117,11 +118,20 @@ struct Team {
     // E = 0.5 sum_i e_i for the Morse pair (e_i holds V).
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
-        __syncthreads();  // previous readers of the position buffer are done
+        constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
+        __syncthreads();  // previous readers of the position and reaction buffers are done
 #pragma unroll
         for (int a = 0; a < A; ++a) {
             const int i = a * T + threadIdx.x;
-            if (i < n) {
+            if constexpr (kTiles) {  // tile layout: each 64-atom tile twice, padded
+                if (i < ((n + kWave - 1) / kWave) * kWave) {
+                    const float4 p = i < n ? make_float4((float)x[0][a], (float)x[1][a],
+                                                         (float)x[2][a], 0.0f)
+                                           : tile_pad(i);
+                    pos32[2 * i - (i & 63)] = p;
+                    pos32[2 * i - (i & 63) + 64] = p;
+                }
+            } else if (i < n) {
                 if constexpr (F32)
                     pos32[i] = make_float4((float)x[0][a], (float)x[1][a], (float)x[2][a], 0.0f);
                 else
@@ -130,7 +140,9 @@ struct Team {
         }
         __syncthreads();
         double e[1][A], o[1];
-        if constexpr (F32)
+        if constexpr (kTiles)
+            pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
+        else if constexpr (F32)
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
         else
             pairs_fp64<A, T, POT>(n, pos64, x, e[0], g, rho);
@@ -536,10 +548,12 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
     __shared__ int claim;
+    __shared__ float tile_rbuf[(MIXED && POT == kPairLJ && kUseTiles<W, A>) ? 6 * T * A : 1];
 
     Team<W, A, POT> tm;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
+    tm.rbuf = tile_rbuf;
     tm.sc = &scratch;
     tm.bank = 0;
     tm.rho = args.rho;
@@ -687,6 +701,7 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
+    __shared__ float tile_rbuf[(MIXED && POT == kPairLJ && kUseTiles<W, A>) ? 6 * T * A : 1];
     const int b = blockIdx.x;
     const int o = offset[b];
     const int n = offset[b + 1] - o;
@@ -697,6 +712,7 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
     Team<W, A, POT> tm;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
+    tm.rbuf = tile_rbuf;
     tm.sc = &scratch;
     tm.bank = 0;
     tm.n = n;
