@@ -255,6 +255,10 @@ typedef struct {
     double rho;          /* Morse range                                     */
 } lj_o_lbfgs;
 
+/* Relative energy change treated as rounding noise by the line search:
+ * 4 ulps of |E| (2^-50). */
+#define LJ_O_LS_RESOLUTION 0x1.0p-50
+
 /* A 3N-vector of one cluster is held as three planes of n doubles. */
 typedef struct {
     double* c[3];
@@ -418,7 +422,13 @@ static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, doub
             gd = dot3(n, g, d, tmp);
         }
 
-        /* Backtracking Armijo line search. */
+        /* Backtracking Armijo line search.  When E_t and E differ by no more
+         * than LJ_O_LS_RESOLUTION |E| (4 ulps of E) the energy test is decided
+         * by the rounding of the energy sums; the trial is then judged by the
+         * derivative form of sufficient decrease (the approximate Armijo
+         * condition of Hager & Zhang, 2005: with the trapezoidal estimate
+         * E_t - E ~ alpha (g.d + g_t.d) / 2, E_t - E <= c1 alpha g.d becomes
+         * g_t.d <= (2 c1 - 1) g.d), which the gradients resolve. */
         double alpha = 1.0, Et = 0.0;
         int ok = 0;
         for (int ls = 0; ls < p->max_ls; ++ls) {
@@ -427,6 +437,11 @@ static int minimize_one(int n, vec3n x, const lj_o_lbfgs* p, double* E_out, doub
             Et = eval(n, xt, gt, tmp, p);
             ++evals;
             if (Et <= fma(p->c1 * alpha, gd, E)) {
+                ok = 1;
+                break;
+            }
+            if (fabs(Et - E) <= LJ_O_LS_RESOLUTION * fabs(E) &&
+                dot3(n, gt, d, tmp) <= (2.0 * p->c1 - 1.0) * gd) {
                 ok = 1;
                 break;
             }
