@@ -116,7 +116,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // eval: (precision, next_pow2(max_n)); large minimiser: (precision).
 std::mutex g_sched_mu;
 std::map<std::pair<int, int>, lj::EvalShape> g_eval_sched;
-int g_large_sched[2] = {1, 1};  // 8 wavefronts x 2 atoms: no register spills
+int g_large_sched[2] = {1, 0};  // FP64: 8 x 2 (no spills); mixed: 16 x 1 (tiled FP32 loop)
 
 int pow2_at_least(int n) {
     int p = 1;

@@ -404,8 +404,9 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 // thread that holds them: tau = a W + w).  The tile's coordinates are staged
 // twice in LDS (pos[128 tau + l] = pos[128 tau + 64 + l] = atom 64 tau + l),
 // so lane l reaches atom (l + k) mod 64 of a tile at an immediate offset.
-//   - diagonal: lane l pairs with l + 1 .. l + 63 of its own tile (every pair
-//     of the tile twice, no reaction);
+//   - diagonal: lane l pairs with l + 1 .. l + 32 (mod 64) of its own tile,
+//     distance 32 on lanes 0-31 only (every pair of the tile once), with the
+//     rotating reaction accumulator below and a final exchange of halves;
 //   - round t = 1 .. nt/2: tile tau pairs with tile J = tau + t (mod nt), every
 //     pair once; for even nt the last round runs on tau < nt/2 only.  The
 //     reaction on J's atom (l + k) accumulates in a register that is rotated
@@ -421,12 +422,23 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 // twice its term to the lane that evaluates it.
 // ---------------------------------------------------------------------------
 template <int W, int A>
-constexpr bool kUseTiles = W * A * kWave >= 512 && W * A * kWave <= 2048;
+constexpr bool kUseTiles = W * A * kWave <= 2048;
+
+// A tile evaluates 32 ring distances per atom within itself, against n
+// partners per atom in the ordered loop: the tiles win above n = 32.
+__device__ __forceinline__ bool tiles_for(int n) { return n > kWave / 2; }
 
 constexpr float kPadSpacing = 1.0e8f;
 
 __device__ __forceinline__ float rol1(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, true));
+}
+
+// Lane l takes lane (l + 32) mod 64's value.
+__device__ __forceinline__ float swap_half_lanes(float v, int lane) {
+    const int b = __float_as_int(v);
+    auto x = __builtin_amdgcn_permlane32_swap(b, b, false, false);  // {lower half, upper half}
+    return __int_as_float(lane < kWave / 2 ? (int)x[1] : (int)x[0]);
 }
 
 __device__ __forceinline__ float4 tile_pad(int i) {
@@ -484,19 +496,42 @@ __device__ __forceinline__ void pairs_tiles(int n, const float4* __restrict__ po
         const float4 pi = pos[128 * tau + lane];
         const float4* src = pos + 128 * tau + lane;
         float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
+        float rx = 0.0f, ry = 0.0f, rz = 0.0f;
 #pragma unroll 1
-        for (int k0 = 1; k0 < kWave; k0 += 9) {  // 63 partners in 7 groups of 9
-            float4 p[9];
+        for (int k0 = 1; k0 <= kWave / 2; k0 += kGroup32) {  // ring distances 1 .. 32
+            float4 p[kGroup32];
 #pragma unroll
-            for (int u = 0; u < 9; ++u) p[u] = src[k0 + u];
+            for (int u = 0; u < kGroup32; ++u) p[u] = src[k0 + u];
 #pragma unroll
-            for (int u = 0; u < 9; ++u)
-                pair_fp32(p[u], false, pi.x, pi.y, pi.z, te, tx, ty, tz);
+            for (int u = 0; u < kGroup32; ++u) {
+                const float dx = pi.x - p[u].x;
+                const float dy = pi.y - p[u].y;
+                const float dz = pi.z - p[u].z;
+                const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float q = __builtin_amdgcn_rcpf(r2);
+                // distance 32 pairs lanes l and l + 32: lanes 0-31 take it
+                const bool dup = (u == kGroup32 - 1) && k0 + u == kWave / 2 && lane >= kWave / 2;
+                const float s6 = dup ? 0.0f : (q * q) * q;
+                te = te + fmaf(s6, s6, -s6);
+                const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+                tx = fmaf(f, dx, tx);
+                ty = fmaf(f, dy, ty);
+                tz = fmaf(f, dz, tz);
+                rx = rol1(rx) - f * dx;
+                ry = rol1(ry) - f * dy;
+                rz = rol1(rz) - f * dz;
+            }
         }
-        e[a] += (double)te;
+        // lane l now holds the reaction on atom l + 32: swap the two halves
+        const float3 r = make_float3(swap_half_lanes(rx, lane), swap_half_lanes(ry, lane),
+                                     swap_half_lanes(rz, lane));
+        e[a] += 2.0 * (double)te;
         g[0][a] += (double)tx;
         g[1][a] += (double)ty;
         g[2][a] += (double)tz;
+        g[0][a] += (double)r.x;
+        g[1][a] += (double)r.y;
+        g[2][a] += (double)r.z;
     }
     const int rounds = nt / 2;
     for (int t = 1; t <= rounds; ++t) {

@@ -119,11 +119,13 @@ struct Team {
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
         constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
+        bool tiles = false;
+        if constexpr (kTiles) tiles = tiles_for(n);
         __syncthreads();  // previous readers of the position and reaction buffers are done
 #pragma unroll
         for (int a = 0; a < A; ++a) {
             const int i = a * T + threadIdx.x;
-            if constexpr (kTiles) {  // tile layout: each 64-atom tile twice, padded
+            if (tiles) {  // tile layout: each 64-atom tile twice, padded
                 if (i < ((n + kWave - 1) / kWave) * kWave) {
                     const float4 p = i < n ? make_float4((float)x[0][a], (float)x[1][a],
                                                          (float)x[2][a], 0.0f)
@@ -140,12 +142,16 @@ struct Team {
         }
         __syncthreads();
         double e[1][A], o[1];
-        if constexpr (kTiles)
-            pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
-        else if constexpr (F32)
+        if constexpr (kTiles) {
+            if (tiles)
+                pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
+            else
+                pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
+        } else if constexpr (F32) {
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
-        else
+        } else {
             pairs_fp64<A, T, POT>(n, pos64, x, e[0], g, rho);
+        }
 #pragma unroll
         for (int a = 0; a < A; ++a)
             if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
@@ -360,6 +366,8 @@ struct History<W, A, false> {
 
 // Phase outcomes (LJ_* statuses, plus the FP32 phase's stall exit).
 constexpr int kStall = 100;
+// Relative energy change that the FP64 line search treats as rounding noise.
+constexpr double kLsResolution = 0x1.0p-50;
 // The FP32 phase treats energy changes as noise-limited only once
 // ||g|| < kNoiseZone * its tolerance: there the Armijo allowance and the exit
 // after five accepted steps without a decrease apply.
@@ -461,6 +469,14 @@ __device__ int lbfgs_run(Team<W, A, POT>& tm, History<W, A, HREG>& H, double (&x
             // step farther from convergence, must show a real decrease
             if (noise_zone && alpha == 1.0) rhs = rhs + p.ls_noise * fabs(E);
             if (Et <= rhs) {
+                ok = true;
+                break;
+            }
+            // FP64: an energy change within the rounding of E (4 ulps) cannot
+            // decide the test; the gradients can (approximate Armijo
+            // condition: g_t.d <= (2 c1 - 1) g.d)
+            if (!F32 && fabs(Et - E) <= kLsResolution * fabs(E) &&
+                tm.dot(gt, d) <= (2.0 * p.c1 - 1.0) * gd) {
                 ok = true;
                 break;
             }
