@@ -153,4 +153,33 @@ def test_autotune_installs_a_valid_schedule(tmp_path):
             ref = r
         for kk in ("xyz", "energy", "iters", "evals", "status"):
             assert np.array_equal(r[kk], ref[kk]), (k, kk)
+    # restore the built-in schedules for the tests that follow
     lj.set_schedule(lj.SCHED_MIN_LARGE, "fp64", 0, 1)
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 0)
+    lj.set_schedule(lj.SCHED_EVAL, "mixed", 1000, *lj.eval_shape_default(1000))
+
+
+TILE_SIZES = [32, 33, 63, 64, 65, 96, 127, 128, 129, 191, 192, 193, 255, 256, 257, 320, 383,
+              448, 511, 512, 513, 640, 767, 896, 1023, 1024, 1025, 1088]
+
+
+@pytest.mark.parametrize("sizes", [TILE_SIZES[:9], TILE_SIZES[9:18], TILE_SIZES[18:]])
+def test_mixed_tiles_across_tile_counts(sizes):
+    """The unique-pair FP32 loop (N > 32) for 1 .. 17 tiles of 64 atoms: odd and
+    even tile counts (half rounds), partial last tiles, every launch shape the
+    batch selects; within the a-priori bound, and Newton's third law holds to
+    the FP32 accumulation bound (sum_i g_i = 0)."""
+    off, x = random_starts(sizes, 950 + len(sizes))
+    xf = x.astype(np.float32).astype(np.float64)
+    announce(f"eval mixed tiles sizes={sizes}")
+    b, xd = to_dev(off, x)
+    E, g = lj.energy_grad(b, xd, "mixed")
+    E, g = host(E), host(g)
+    Eo, go = O.energy_grad(off, xf)
+    eabs, gabs = O.abs_sums(off, xf)
+    assert np.all(np.abs(E - Eo) <= 128 * U32 * eabs)
+    assert np.all(np.abs(g - go) <= 128 * U32 * gabs + 1e-300)
+    for k in range(len(sizes)):
+        a, z = off[k], off[k + 1]
+        net = np.abs(g[:, a:z].sum(axis=1))
+        assert np.all(net <= 128 * U32 * gabs[:, a:z].sum(axis=1))
