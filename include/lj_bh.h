@@ -243,8 +243,9 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
  *                      precision and max_n rounded up to a power of two;
  *                      64*W*A must be >= max_n.
  *   LJ_SCHED_MIN_LARGE minimiser shape for clusters of 257..1024 atoms, keyed by
- *                      precision: w = 0 (16 wavefronts x 1 atom), 1 (8 x 2,
- *                      the default) or 2 (4 x 4); a is ignored.
+ *                      precision: w = 0 (16 wavefronts x 1 atom, the LJ_MIXED
+ *                      default), 1 (8 x 2, the LJ_FP64 default) or 2 (4 x 4);
+ *                      a is ignored.
  * Results never depend on the schedule in LJ_FP64 (fixed summation order).
  */
 #define LJ_SCHED_EVAL 0

@@ -116,7 +116,8 @@ def test_schedule_table_validation():
     assert lj.get_schedule(lj.SCHED_EVAL, "fp64", 600) == (4, 4)  # same power-of-two key
     assert lj.get_schedule(lj.SCHED_EVAL, "mixed", 1000) == (16, 1)
     lj.set_schedule(lj.SCHED_EVAL, "fp64", 1000, 16, 1)
-    assert lj.get_schedule(lj.SCHED_MIN_LARGE, "mixed")[0] == 1  # default 8 x 2
+    assert lj.get_schedule(lj.SCHED_MIN_LARGE, "mixed")[0] == 0  # default 16 x 1
+    assert lj.get_schedule(lj.SCHED_MIN_LARGE, "fp64")[0] == 1  # default 8 x 2
     lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 2)
     assert lj.get_schedule(lj.SCHED_MIN_LARGE, "mixed")[0] == 2
-    lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 1)
+    lj.set_schedule(lj.SCHED_MIN_LARGE, "mixed", 0, 0)
