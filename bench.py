@@ -50,6 +50,30 @@ def load_traffic(key):
     return t[key]["hbm_bytes_per_launch"]
 
 
+def load_issue(key, launch_ms):
+    """VALU issue rate of the minimiser from committed SQ counter runs, if current.
+
+    The kernel runs one wavefront per SIMD, so its bound is instruction issue:
+    the peak is one wave64 VALU instruction per SIMD every 4 cycles
+    (256 CUs x 4 SIMDs x 2.4 GHz / 4)."""
+    path = os.path.join(ROOT, "profiles", "issue.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha") != kernel_source_hash() or key not in t:
+        return None
+    k, peak = t[key], t["valu_issue_peak_per_s"]
+    rate = k["valu_insts_per_launch"] / (launch_ms * 1e-3)
+    return {"valu_insts_per_launch": k["valu_insts_per_launch"],
+            "valu_per_iteration": round(k["valu_per_iteration"], 1),
+            "cycles_per_instruction": round(k["cycles_per_instruction"], 2),
+            "achieved_ginst_per_s": rate / 1e9, "peak_ginst_per_s": peak / 1e9,
+            "frac": rate / peak,
+            "counted_tflop_per_s": (k["counted_flop_fp32"] + k["counted_flop_fp64"])
+            / (launch_ms * 1e-3) / 1e12}
+
+
 def pair_kernel(lj, large_clusters, dev, stream, torch):
     """lj_energy_grad_batch on 256 clusters of N = 1000, FP32-pair and FP64."""
     wl4 = large_clusters()
@@ -266,9 +290,12 @@ def main():
     B = batch.num
     if args.only in ("mixed", "fp64"):
         r = run(args.only, args.steps, args.warmup)
+        it, ev = r["host"]["iters"].astype(np.int64), r["host"]["evals"].astype(np.int64)
         print(json.dumps({"only": args.only, "kernel_ms": r["kern_ms"],
                           "minimisations_per_s": B * args.steps / r["wall"],
-                          "pair_evals_per_launch": r["pair_evals"]}), flush=True)
+                          "pair_evals_per_launch": r["pair_evals"],
+                          "iters_sum": int(it.sum()), "iters_max": int(it.max()),
+                          "evals_sum": int(ev.sum()), "evals_max": int(ev.max())}), flush=True)
         return
     if args.only == "pair":
         args.no_cpu = True
@@ -336,7 +363,8 @@ def main():
             "kernel": "minimize_kernel<mixed, 1 wave, 1 atom/lane, history in registers>",
             "note": "27 FLOP per unique pair evaluation (both phases) over the launch; "
                     "peak = FP32 vector 157.3 TFLOP/s (packed FP32 is disabled in this build)",
-            "flop_per_launch": flops, "launch_ms": mixed["kern_ms"]}
+            "flop_per_launch": flops, "launch_ms": mixed["kern_ms"],
+            "valu_issue": load_issue("minimize_mixed_lj38_1024", mixed["kern_ms"])}
 
     line = {
         "metric": "local minimisations/sec and LJ pair-evals/sec, FP64 vs mixed, 1 MI355X",
