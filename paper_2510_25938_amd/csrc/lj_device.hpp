@@ -479,6 +479,104 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
     return make_float3(rol1(rx), rol1(ry), rol1(rz));
 }
 
+// ---------------------------------------------------------------------------
+// FP32 Eq. (1) over unique pairs for one-wavefront clusters of
+// kRingMin <= n <= 41 atoms: a ring of period n.  Lane l holds atom l mod n
+// (lanes n .. 63 are replicas) and pairs with atom (l + k) mod n for
+// k = 1 .. n/2; for even n the distance n/2 is taken by the lanes whose atom
+// is below n/2 only, so every unique pair is evaluated once by a real lane.
+// The reaction on the partner accumulates in a register rotated one lane per
+// step (wave_rol:1): lane l receives lane l + 1's sum, which followed atom
+// (l + 1) mod n + k - 1 = l mod n + k, for every lane except 63, which wraps to
+// lane 0.  That one wrong value enters at lane 63 and moves down one lane per
+// step, so after K steps lanes 0 .. 63 - K are exact, and these include every
+// real lane when K <= 64 - n.  Steps run in groups of kRingGroup (padded steps
+// add zero but rotate); the result on lane l is the reaction on atom
+// (l + K) mod n, returned to its owner through LDS.  The coordinates are staged
+// as pos[j] = atom j mod n for j < 64 + K.  FP32 sums cover at most K <= 32
+// terms and are added into FP64.  e_i follows the ordered-pair convention of
+// pairs_mixed, as in pairs_tiles.
+// ---------------------------------------------------------------------------
+constexpr int kRingGroup = 4;
+constexpr int kRingMin = 5;
+
+// Steps of the ring for n atoms (n/2 rounded up to whole groups).
+__device__ __forceinline__ int ring_steps(int n) {
+    return (n / 2 + kRingGroup - 1) / kRingGroup * kRingGroup;
+}
+__device__ __forceinline__ bool ring_for(int n) {
+    return n >= kRingMin && ring_steps(n) <= kWave - n;
+}
+
+template <bool LAST>
+__device__ __forceinline__ void ring_group(const float4 pi, const float4* __restrict__ src,
+                                           int k0, int K, bool upper, float& te, float& tx,
+                                           float& ty, float& tz, float& rx, float& ry,
+                                           float& rz) {
+    float4 p[kRingGroup];
+#pragma unroll
+    for (int u = 0; u < kRingGroup; ++u) p[u] = src[k0 + u];
+#pragma unroll
+    for (int u = 0; u < kRingGroup; ++u) {
+        const float dx = pi.x - p[u].x;
+        const float dy = pi.y - p[u].y;
+        const float dz = pi.z - p[u].z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        float q = __builtin_amdgcn_rcpf(r2);
+        if constexpr (LAST) {
+            // padded steps, and distance n/2 on the upper lanes, add nothing
+            const int k = k0 + u;
+            if (k > K || (k == K && upper)) q = 0.0f;
+        }
+        const float s6 = (q * q) * q;
+        te = te + fmaf(s6, s6, -s6);
+        const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+        tx = fmaf(f, dx, tx);
+        ty = fmaf(f, dy, ty);
+        tz = fmaf(f, dz, tz);
+        rx = rol1(rx) - f * dx;
+        ry = rol1(ry) - f * dy;
+        rz = rol1(rz) - f * dz;
+    }
+}
+
+__device__ __forceinline__ void pairs_ring(int n, const float4* __restrict__ pos,
+                                           float* __restrict__ rbuf, double& e,
+                                           double (&g)[3][1]) {
+    const int lane = threadIdx.x;  // one wavefront
+    const int K = n / 2;
+    const int KS = ring_steps(n);
+    const int al = lane % n;
+    const bool upper = (n % 2 == 0) && al >= K;
+    const float4 pi = pos[lane];
+    const float4* src = pos + lane;
+    float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
+    float rx = 0.0f, ry = 0.0f, rz = 0.0f;
+    int k0 = 1;
+#pragma unroll 1
+    for (; k0 + kRingGroup - 1 < K; k0 += kRingGroup)
+        ring_group<false>(pi, src, k0, K, upper, te, tx, ty, tz, rx, ry, rz);
+#pragma unroll 1
+    for (; k0 <= KS; k0 += kRingGroup)
+        ring_group<true>(pi, src, k0, K, upper, te, tx, ty, tz, rx, ry, rz);
+    if (lane < n) {  // lane l holds the reaction on atom (l + KS) mod n, KS < n
+        int t = lane + KS;
+        if (t >= n) t -= n;
+        rbuf[t] = rx;
+        rbuf[kWave + t] = ry;
+        rbuf[2 * kWave + t] = rz;
+    }
+    __syncthreads();
+    e = 0.0;
+    g[0][0] = g[1][0] = g[2][0] = 0.0;
+    if (lane < n) {
+        e = 2.0 * (double)te;
+        g[0][0] = (double)tx + (double)rbuf[lane];
+        g[1][0] = (double)ty + (double)rbuf[kWave + lane];
+        g[2][0] = (double)tz + (double)rbuf[2 * kWave + lane];
+    }
+}
+
 template <int W, int A>
 __device__ __forceinline__ void pairs_tiles(int n, const float4* __restrict__ pos,
                                             float* __restrict__ rbuf, double (&e)[A],

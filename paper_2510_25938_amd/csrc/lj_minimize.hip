@@ -119,13 +119,22 @@ struct Team {
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
         constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
-        bool tiles = false;
-        if constexpr (kTiles) tiles = tiles_for(n);
+        constexpr bool kRing = kTiles && W == 1 && A == 1;
+        bool ring = false, tiles = false;
+        if constexpr (kRing) ring = ring_for(n);
+        if constexpr (kTiles) tiles = !ring && tiles_for(n);
         __syncthreads();  // previous readers of the position and reaction buffers are done
 #pragma unroll
         for (int a = 0; a < A; ++a) {
             const int i = a * T + threadIdx.x;
-            if (tiles) {  // tile layout: each 64-atom tile twice, padded
+            if (ring) {  // ring layout: pos[j] = atom j mod n for j < 64 + steps
+                if (i < n) {
+                    const float4 p = make_float4((float)x[0][a], (float)x[1][a], (float)x[2][a],
+                                                 0.0f);
+                    const int end = kWave + ring_steps(n);
+                    for (int j = i; j < end; j += n) pos32[j] = p;
+                }
+            } else if (tiles) {  // tile layout: each 64-atom tile twice, padded
                 if (i < ((n + kWave - 1) / kWave) * kWave) {
                     const float4 p = i < n ? make_float4((float)x[0][a], (float)x[1][a],
                                                          (float)x[2][a], 0.0f)
@@ -143,10 +152,13 @@ struct Team {
         __syncthreads();
         double e[1][A], o[1];
         if constexpr (kTiles) {
-            if (tiles)
+            if (ring) {
+                if constexpr (kRing) pairs_ring(n, pos32, rbuf, e[0][0], g);
+            } else if (tiles) {
                 pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
-            else
+            } else {
                 pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
+            }
         } else if constexpr (F32) {
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
         } else {

@@ -159,6 +159,31 @@ def test_autotune_installs_a_valid_schedule(tmp_path):
     lj.set_schedule(lj.SCHED_EVAL, "mixed", 1000, *lj.eval_shape_default(1000))
 
 
+RING_SIZES = list(range(0, 65))  # ring n = 5 .. 41; ordered below, 64-atom tile above
+
+
+@pytest.mark.parametrize("sizes", [RING_SIZES[:33], RING_SIZES[33:]])
+def test_mixed_ring_across_sizes(sizes):
+    """The one-wavefront unique-pair FP32 ring (5 <= N <= 41, replicas in the
+    lanes above N, a rotated reaction register) and its neighbours (the ordered
+    loop below, the 64-atom tile above) for every N up to 64: within the
+    a-priori bound, and Newton's third law to the FP32 accumulation bound."""
+    off, x = random_starts(sizes, 940 + len(sizes))
+    xf = x.astype(np.float32).astype(np.float64)
+    announce(f"eval mixed ring sizes={sizes[0]}..{sizes[-1]}")
+    b, xd = to_dev(off, x)
+    E, g = lj.energy_grad(b, xd, "mixed")
+    E, g = host(E), host(g)
+    Eo, go = O.energy_grad(off, xf)
+    eabs, gabs = O.abs_sums(off, xf)
+    assert np.all(np.abs(E - Eo) <= 128 * U32 * eabs)
+    assert np.all(np.abs(g - go) <= 128 * U32 * gabs + 1e-300)
+    for k in range(len(sizes)):
+        a, z = off[k], off[k + 1]
+        net = np.abs(g[:, a:z].sum(axis=1))
+        assert np.all(net <= 128 * U32 * gabs[:, a:z].sum(axis=1))
+
+
 TILE_SIZES = [32, 33, 63, 64, 65, 96, 127, 128, 129, 191, 192, 193, 255, 256, 257, 320, 383,
               448, 511, 512, 513, 640, 767, 896, 1023, 1024, 1025, 1088]
 
