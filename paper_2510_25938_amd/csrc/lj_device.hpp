@@ -480,11 +480,12 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
 }
 
 // ---------------------------------------------------------------------------
-// FP32 Eq. (1) over unique pairs for one-wavefront clusters of
-// kRingMin <= n <= 41 atoms: a ring of period n.  Lane l holds atom l mod n
-// (lanes n .. 63 are replicas) and pairs with atom (l + k) mod n for
-// k = 1 .. n/2; for even n the distance n/2 is taken by the lanes whose atom
-// is below n/2 only, so every unique pair is evaluated once by a real lane.
+// FP32 pair terms (Eq. (1) or the Morse pair) over unique pairs for
+// one-wavefront clusters of kRingMin <= n <= 41 atoms: a ring of period n.
+// Lane l holds atom l mod n (lanes n .. 63 are replicas) and pairs with atom
+// (l + k) mod n for k = 1 .. n/2; for even n the distance n/2 is taken by the
+// lanes whose atom is below n/2 only, so every unique pair is evaluated once
+// by a real lane.
 // The reaction on the partner accumulates in a register rotated one lane per
 // step (wave_rol:1): lane l receives lane l + 1's sum, which followed atom
 // (l + 1) mod n + k - 1 = l mod n + k, for every lane except 63, which wraps to
@@ -498,7 +499,7 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
 // pairs_mixed, as in pairs_tiles.
 // ---------------------------------------------------------------------------
 constexpr int kRingGroup = 4;
-constexpr int kRingMin = 5;
+constexpr int kRingMin = 20;  // below, the ordered loop is as fast (staging and readout)
 
 // Steps of the ring for n atoms (n/2 rounded up to whole groups).
 __device__ __forceinline__ int ring_steps(int n) {
@@ -508,11 +509,11 @@ __device__ __forceinline__ bool ring_for(int n) {
     return n >= kRingMin && ring_steps(n) <= kWave - n;
 }
 
-template <bool LAST>
+template <bool LAST, int POT>
 __device__ __forceinline__ void ring_group(const float4 pi, const float4* __restrict__ src,
-                                           int k0, int K, bool upper, float& te, float& tx,
-                                           float& ty, float& tz, float& rx, float& ry,
-                                           float& rz) {
+                                           int k0, int K, bool upper, float rho, float c,
+                                           float& te, float& tx, float& ty, float& tz,
+                                           float& rx, float& ry, float& rz) {
     float4 p[kRingGroup];
 #pragma unroll
     for (int u = 0; u < kRingGroup; ++u) p[u] = src[k0 + u];
@@ -522,15 +523,28 @@ __device__ __forceinline__ void ring_group(const float4 pi, const float4* __rest
         const float dy = pi.y - p[u].y;
         const float dz = pi.z - p[u].z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        float q = __builtin_amdgcn_rcpf(r2);
+        // padded steps, and distance n/2 on the upper lanes, add nothing
+        bool skip = false;
         if constexpr (LAST) {
-            // padded steps, and distance n/2 on the upper lanes, add nothing
             const int k = k0 + u;
-            if (k > K || (k == K && upper)) q = 0.0f;
+            skip = k > K || (k == K && upper);
         }
-        const float s6 = (q * q) * q;
-        te = te + fmaf(s6, s6, -s6);
-        const float f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+        float ep, f;
+        if constexpr (POT == kPairMorse) {
+            const float r = __builtin_amdgcn_sqrtf(r2);
+            float t = __builtin_amdgcn_exp2f(fmaf(-rho, r, rho) * 1.44269504f);
+            float q = __builtin_amdgcn_rcpf(r);
+            if (skip) t = q = 0.0f;
+            ep = t * (t - 2.0f);
+            f = ((c * t) * (t - 1.0f)) * q;
+        } else {
+            float q = __builtin_amdgcn_rcpf(r2);
+            if (skip) q = 0.0f;
+            const float s6 = (q * q) * q;
+            ep = fmaf(s6, s6, -s6);
+            f = (q * s6) * fmaf(-48.0f, s6, 24.0f);
+        }
+        te = te + ep;
         tx = fmaf(f, dx, tx);
         ty = fmaf(f, dy, ty);
         tz = fmaf(f, dz, tz);
@@ -540,14 +554,16 @@ __device__ __forceinline__ void ring_group(const float4 pi, const float4* __rest
     }
 }
 
+template <int POT>
 __device__ __forceinline__ void pairs_ring(int n, const float4* __restrict__ pos,
                                            float* __restrict__ rbuf, double& e,
-                                           double (&g)[3][1]) {
+                                           double (&g)[3][1], double rho) {
     const int lane = threadIdx.x;  // one wavefront
     const int K = n / 2;
     const int KS = ring_steps(n);
     const int al = lane % n;
     const bool upper = (n % 2 == 0) && al >= K;
+    const float rf = (float)rho, cf = -2.0f * rf;
     const float4 pi = pos[lane];
     const float4* src = pos + lane;
     float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
@@ -555,10 +571,10 @@ __device__ __forceinline__ void pairs_ring(int n, const float4* __restrict__ pos
     int k0 = 1;
 #pragma unroll 1
     for (; k0 + kRingGroup - 1 < K; k0 += kRingGroup)
-        ring_group<false>(pi, src, k0, K, upper, te, tx, ty, tz, rx, ry, rz);
+        ring_group<false, POT>(pi, src, k0, K, upper, rf, cf, te, tx, ty, tz, rx, ry, rz);
 #pragma unroll 1
     for (; k0 <= KS; k0 += kRingGroup)
-        ring_group<true>(pi, src, k0, K, upper, te, tx, ty, tz, rx, ry, rz);
+        ring_group<true, POT>(pi, src, k0, K, upper, rf, cf, te, tx, ty, tz, rx, ry, rz);
     if (lane < n) {  // lane l holds the reaction on atom (l + KS) mod n, KS < n
         int t = lane + KS;
         if (t >= n) t -= n;

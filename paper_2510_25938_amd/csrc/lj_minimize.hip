@@ -26,7 +26,7 @@ struct Team {
     static constexpr int NVMAX = 4 * A;
     double4* pos64;
     float4* pos32;
-    float* rbuf;  // reaction buffers of the tiled FP32 loop (kUseTiles teams)
+    float* rbuf;  // reaction buffers of the FP32 tiles and the one-wavefront ring
     TeamScratch<W, NVMAX>* sc;
     int bank;
     int n;
@@ -119,7 +119,7 @@ struct Team {
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
         constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
-        constexpr bool kRing = kTiles && W == 1 && A == 1;
+        constexpr bool kRing = F32 && W == 1 && A == 1;
         bool ring = false, tiles = false;
         if constexpr (kRing) ring = ring_for(n);
         if constexpr (kTiles) tiles = !ring && tiles_for(n);
@@ -151,14 +151,10 @@ struct Team {
         }
         __syncthreads();
         double e[1][A], o[1];
-        if constexpr (kTiles) {
-            if (ring) {
-                if constexpr (kRing) pairs_ring(n, pos32, rbuf, e[0][0], g);
-            } else if (tiles) {
-                pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
-            } else {
-                pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
-            }
+        if (ring) {
+            if constexpr (kRing) pairs_ring<POT>(n, pos32, rbuf, e[0][0], g, rho);
+        } else if (tiles) {
+            if constexpr (kTiles) pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
         } else if constexpr (F32) {
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
         } else {
@@ -576,7 +572,9 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
     __shared__ int claim;
-    __shared__ float tile_rbuf[(MIXED && POT == kPairLJ && kUseTiles<W, A>) ? 6 * T * A : 1];
+    __shared__ float tile_rbuf[(MIXED && ((POT == kPairLJ && kUseTiles<W, A>) || (W == 1 && A == 1)))
+                                   ? 6 * T * A
+                                   : 1];
 
     Team<W, A, POT> tm;
     tm.pos64 = pos_buf;
@@ -729,7 +727,9 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
-    __shared__ float tile_rbuf[(MIXED && POT == kPairLJ && kUseTiles<W, A>) ? 6 * T * A : 1];
+    __shared__ float tile_rbuf[(MIXED && ((POT == kPairLJ && kUseTiles<W, A>) || (W == 1 && A == 1)))
+                                   ? 6 * T * A
+                                   : 1];
     const int b = blockIdx.x;
     const int o = offset[b];
     const int n = offset[b + 1] - o;

@@ -78,6 +78,29 @@ def test_mixed_error_bound(shape):
         assert np.all(np.abs(g[:, a:z] - go[:, a:z]) <= c * gabs[:, a:z] + 1e-300)
 
 
+@pytest.mark.parametrize("lo,hi,rho", [(0, 33, 6.0), (33, 65, 3.0)])
+def test_mixed_ring_across_sizes(lo, hi, rho):
+    """Every N up to 64 for the Morse pair: the one-wavefront FP32 ring
+    (20 <= N <= 41) and the ordered loop around it, within the derived bound;
+    Newton's third law to the FP32 accumulation bound."""
+    sizes = list(range(lo, hi))
+    off, x = random_starts(sizes, 720 + lo)
+    xf = x.astype(np.float32).astype(np.float64)
+    announce(f"morse eval mixed ring sizes={lo}..{hi - 1} rho={rho}")
+    b, xd = morse_dev(off, x, rho)
+    E, g = lj.energy_grad(b, xd, "mixed")
+    E, g = host(E), host(g)
+    Eo, go = O.energy_grad(off, xf, "morse", rho)
+    eabs, gabs = O.abs_sums(off, xf, "morse", rho)
+    for k in range(len(sizes)):
+        a, z = off[k], off[k + 1]
+        span = np.ptp(xf[:, a:z], axis=1) if z > a else np.zeros(3)
+        c = (12.0 * rho * float(np.linalg.norm(span)) + 128.0) * U32
+        assert abs(E[k] - Eo[k]) <= c * eabs[k]
+        assert np.all(np.abs(g[:, a:z] - go[:, a:z]) <= c * gabs[:, a:z] + 1e-300)
+        assert np.all(np.abs(g[:, a:z].sum(axis=1)) <= c * gabs[:, a:z].sum(axis=1) + 1e-300)
+
+
 @pytest.mark.parametrize("sizes,rho", [([2, 3, 4, 13, 38, 64], 6.0), ([80, 13, 128], 3.0),
                                        ([150, 200], 10.0), ([300, 13], 6.0)])
 def test_fp64_minimize_bitwise(sizes, rho):
