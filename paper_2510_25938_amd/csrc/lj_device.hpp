@@ -89,6 +89,56 @@ __device__ __forceinline__ double wave_sum(double v) {
     return a + b;
 }
 
+constexpr int kDppRor4 = 0x124;   // row_ror:4  (lane i of a row takes lane i - 4)
+constexpr int kDppRor8 = 0x128;   // row_ror:8  (i takes i ^ 8)
+constexpr int kDppRor12 = 0x12C;  // row_ror:12 (i takes i + 4)
+
+// Lane l takes lane l ^ 4: the rotation by 12 fills banks 0 and 2 of every
+// row (lanes 0-3, 8-11), the rotation by 4 then fills banks 1 and 3.
+__device__ __forceinline__ double dpp_xor4(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    int2 r;
+    r.x = __builtin_amdgcn_mov_dpp(b.x, kDppRor12, 0xF, 0x5, false);
+    r.y = __builtin_amdgcn_mov_dpp(b.y, kDppRor12, 0xF, 0x5, false);
+    r.x = __builtin_amdgcn_update_dpp(r.x, b.x, kDppRor4, 0xF, 0xA, false);
+    r.y = __builtin_amdgcn_update_dpp(r.y, b.y, kDppRor4, 0xF, 0xA, false);
+    return *reinterpret_cast<double*>(&r);
+}
+
+constexpr int kDppNewBcast = 0x150;  // row_newbcast:k = 0x150 + k (lane k of each row to the row)
+
+// Four sums over the 64 lanes, each with exactly the pairings of wave_sum,
+// sharing one exchange per level: at the first level (lanes 2^0 apart) even
+// lanes keep a and c and hand b and d to their odd partner, which keeps b and
+// d; at the second (2^1 apart) each lane keeps one of its two partial sums and
+// hands over the other, so that lane l then carries value l mod 4.  The
+// remaining levels pair lanes 4, 8, 16 and 32 apart, which preserves the lane
+// residue mod 4.  Each addition combines the same two blocks of lanes as in
+// wave_sum (IEEE addition is commutative), so every result has wave_sum's
+// bits.  Every row then holds the four totals in its lanes 0 .. 3, and
+// row_newbcast hands each total to all lanes (a vector value, like
+// wave_sum's: a scalar read-out changes how the compiler allocates the
+// minimiser's registers and spills the L-BFGS state).
+__device__ __forceinline__ void wave_sum4(double a, double b, double c, double d,
+                                          double (&out)[4]) {
+    const int lane = __lane_id();
+    const bool odd = (lane & 1) != 0, hi = (lane & 2) != 0;
+    const double u = (odd ? b : a) + dpp<kDppXor1>(odd ? a : b);
+    const double w = (odd ? d : c) + dpp<kDppXor1>(odd ? c : d);
+    double v = (hi ? w : u) + dpp<kDppXor2>(hi ? u : w);
+    v = v + dpp_xor4(v);
+    v = v + dpp<kDppRor8>(v);
+    double x, y;
+    swap_rows16(v, x, y);
+    v = x + y;
+    swap_halves32(v, x, y);
+    v = x + y;
+    out[0] = dpp<kDppNewBcast + 0>(v);
+    out[1] = dpp<kDppNewBcast + 1>(v);
+    out[2] = dpp<kDppNewBcast + 2>(v);
+    out[3] = dpp<kDppNewBcast + 3>(v);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp<kDppXor1>(v));
     v = fmax(v, dpp<kDppXor2>(v));
@@ -130,9 +180,17 @@ __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV
     static_assert(NV * A <= NVMAX, "scratch too small");
     double ws[NV][A];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
+    for (int a = 0; a < A; ++a) {
+        if constexpr (NV == 4) {
+            double o4[4];
+            wave_sum4(vals[0][a], vals[1][a], vals[2][a], vals[3][a], o4);
 #pragma unroll
-        for (int a = 0; a < A; ++a) ws[k][a] = wave_sum(vals[k][a]);
+            for (int k = 0; k < 4; ++k) ws[k][a] = o4[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) ws[k][a] = wave_sum(vals[k][a]);
+        }
+    }
     if constexpr (W == 1) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
