@@ -77,11 +77,28 @@ __device__ __forceinline__ void swap_halves32(double v, double& lo, double& hi) 
     hi = *reinterpret_cast<double*>(&h);
 }
 
+// Row 0's value in every lane: row_bcast:15 copies lane 15 into row 1, then
+// row_bcast:31 copies lane 31 into rows 2 and 3.
+__device__ __forceinline__ double bcast_row0(double v) {
+    int2 b = *reinterpret_cast<int2*>(&v);
+    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, 0x142, 0x2, 0xF, false);
+    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, 0x142, 0x2, 0xF, false);
+    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, 0x143, 0xC, 0xF, false);
+    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, 0x143, 0xC, 0xF, false);
+    return *reinterpret_cast<double*>(&b);
+}
+
+// L = 64 leaves, or L = 16 when only lanes 0-15 can hold nonzero values (a
+// cluster of at most 16 atoms): then the sum is the tree of row 0 (the same
+// 16-leaf tree the pairwise sum pads N <= 16 to), broadcast to every lane.
+template <int L = kWave>
 __device__ __forceinline__ double wave_sum(double v) {
+    static_assert(L == 16 || L == kWave, "16 or 64 leaves");
     v = v + dpp<kDppXor1>(v);
     v = v + dpp<kDppXor2>(v);
     v = v + dpp<kDppHalfMirror>(v);
     v = v + dpp<kDppMirror>(v);
+    if constexpr (L == 16) return bcast_row0(v);
     double a, b;
     swap_rows16(v, a, b);  // a: even row's value in both rows, b: odd row's
     v = a + b;
@@ -139,11 +156,14 @@ __device__ __forceinline__ void wave_sum4(double a, double b, double c, double d
     out[3] = dpp<kDppNewBcast + 3>(v);
 }
 
+template <int L = kWave>
 __device__ __forceinline__ double wave_max(double v) {
+    static_assert(L == 16 || L == kWave, "16 or 64 leaves");
     v = fmax(v, dpp<kDppXor1>(v));
     v = fmax(v, dpp<kDppXor2>(v));
     v = fmax(v, dpp<kDppHalfMirror>(v));
     v = fmax(v, dpp<kDppMirror>(v));
+    if constexpr (L == 16) return bcast_row0(v);
     double a, b;
     swap_rows16(v, a, b);
     v = fmax(a, b);
@@ -174,10 +194,11 @@ struct TeamScratch {
 // for atom slot a; the result for k is tree_a( tree_w( wave_sum ) ), i.e. the
 // pairwise sum over the atom index i = a*T + w*64 + lane padded to a power of
 // two.  Every thread of the team receives every result.
-template <int W, int A, int NV, int NVMAX>
+template <int W, int A, int NV, int NVMAX, int L = kWave>
 __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV],
                                          TeamScratch<W, NVMAX>& sc, int& bank) {
     static_assert(NV * A <= NVMAX, "scratch too small");
+    static_assert(L == kWave || (W == 1 && A == 1), "16 leaves: one wavefront, one slot");
     double ws[NV][A];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -188,7 +209,7 @@ __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV
             for (int k = 0; k < 4; ++k) ws[k][a] = o4[k];
         } else {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) ws[k][a] = wave_sum(vals[k][a]);
+            for (int k = 0; k < NV; ++k) ws[k][a] = wave_sum<L>(vals[k][a]);
         }
     }
     if constexpr (W == 1) {
@@ -225,13 +246,13 @@ __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV
     }
 }
 
-template <int W, int A, int NVMAX>
+template <int W, int A, int NVMAX, int L = kWave>
 __device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<W, NVMAX>& sc,
                                            int& bank) {
     double m = vals[0];
 #pragma unroll
     for (int a = 1; a < A; ++a) m = fmax(m, vals[a]);
-    m = wave_max(m);
+    m = wave_max<L>(m);
     if constexpr (W == 1) {
         return m;
     } else {

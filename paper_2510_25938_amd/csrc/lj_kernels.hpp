@@ -65,11 +65,13 @@ hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const in
 int class_of(int n);
 int class_block(int c, int large);
 size_t class_hist_bytes_per_wg(int c, int large);
-const void* minimize_kernel_for(int mixed, int pot, int c, int large);
+// small16: the class-0 kernel for batches whose clusters all have at most 16
+// atoms (its reductions run over one 16-lane row).
+const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool small16);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);
-hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,
-                                 hipStream_t st);
+hipError_t launch_minimize_class(int mixed, int c, int large, bool small16, int grid,
+                                 const MinArgs& a, hipStream_t st);
 
 struct BhDev {
     int cands;

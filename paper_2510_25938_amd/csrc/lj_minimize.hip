@@ -20,7 +20,7 @@ namespace lj {
 // ---------------------------------------------------------------------------
 // Team: LDS buffers and the collective operations of one workgroup.
 // ---------------------------------------------------------------------------
-template <int W, int A, int POT>
+template <int W, int A, int POT, int L = kWave>
 struct Team {
     static constexpr int T = kWave * W;
     static constexpr int NVMAX = 4 * A;
@@ -38,7 +38,7 @@ struct Team {
         double p[1][A], o[1];
 #pragma unroll
         for (int a = 0; a < A; ++a) p[0][a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
-        team_sum<W, A, 1, NVMAX>(p, o, *sc, bank);
+        team_sum<W, A, 1, NVMAX, L>(p, o, *sc, bank);
         return o[0];
     }
 
@@ -54,7 +54,7 @@ struct Team {
             p[2][a] = fma(s[2][a], s[2][a], fma(s[1][a], s[1][a], s[0][a] * s[0][a]));
             p[3][a] = fma(w[2][a], w[2][a], fma(w[1][a], w[1][a], w[0][a] * w[0][a]));
         }
-        team_sum<W, A, 4, NVMAX>(p, o, *sc, bank);
+        team_sum<W, A, 4, NVMAX, L>(p, o, *sc, bank);
         sy = o[0];
         yy = o[1];
         ss = o[2];
@@ -66,7 +66,7 @@ struct Team {
         double m[A];
 #pragma unroll
         for (int a = 0; a < A; ++a) m[a] = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
-        return team_max<W, A, NVMAX>(m, *sc, bank);
+        return team_max<W, A, NVMAX, L>(m, *sc, bank);
     }
 
     // u.v and the largest per-atom squared norm of v, with the same values as
@@ -82,8 +82,8 @@ struct Team {
             m = a == 0 ? n2 : fmax(m, n2);
         }
 #pragma unroll
-        for (int a = 0; a < A; ++a) ws[a] = wave_sum(p[a]);
-        m = wave_max(m);
+        for (int a = 0; a < A; ++a) ws[a] = wave_sum<L>(p[a]);
+        m = wave_max<L>(m);
         if constexpr (W == 1) {
             uv = tree<A>(ws);
             vmax2 = m;
@@ -163,7 +163,7 @@ struct Team {
 #pragma unroll
         for (int a = 0; a < A; ++a)
             if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
-        team_sum<W, A, 1, NVMAX>(e, o, *sc, bank);
+        team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
         return (POT == kPairMorse ? 0.5 : 2.0) * o[0];
     }
 };
@@ -385,8 +385,8 @@ constexpr double kNoiseZone = 100.0;
 constexpr int kZonePatience = 30;
 
 // E and g at x with FP32 pair arithmetic when f32 (only compiled when CAN32).
-template <bool CAN32, int W, int A, int POT>
-__device__ __forceinline__ double eval_phase(Team<W, A, POT>& tm, const double (&x)[3][A],
+template <bool CAN32, int W, int A, int POT, int L>
+__device__ __forceinline__ double eval_phase(Team<W, A, POT, L>& tm, const double (&x)[3][A],
                                              double (&g)[3][A], bool f32) {
     if constexpr (CAN32) {
         if (f32) return tm.template eval<true>(x, g);
@@ -399,8 +399,8 @@ __device__ __forceinline__ double eval_phase(Team<W, A, POT>& tm, const double (
 // single copy of this loop for both phases) selects the FP32 pair arithmetic,
 // the Armijo noise allowance and the stall exit of the mixed path's first
 // phase.
-template <bool CAN32, int W, int A, bool HREG, int POT>
-__device__ int lbfgs_run(Team<W, A, POT>& tm, History<W, A, HREG>& H, double (&x)[3][A],
+template <bool CAN32, int W, int A, bool HREG, int POT, int L>
+__device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double (&x)[3][A],
                          double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
                          const LbfgsDev& p, double gtol, int max_iter, bool f32_flag) {
     const bool F32 = CAN32 && f32_flag;
@@ -566,7 +566,7 @@ __device__ int lbfgs_run(Team<W, A, POT>& tm, History<W, A, HREG>& H, double (&x
 // ---------------------------------------------------------------------------
 // Persistent minimiser kernel: one launch per size class.
 // ---------------------------------------------------------------------------
-template <int MIXED, int W, int A, bool HREG, int POT>
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave>
 __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                                    ? 6 * T * A
                                    : 1];
 
-    Team<W, A, POT> tm;
+    Team<W, A, POT, L> tm;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
     tm.rbuf = tile_rbuf;
@@ -853,13 +853,16 @@ size_t class_hist_bytes_per_wg(int c, int large) {
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
-template <int MIXED, int W, int A, bool HREG, int POT>
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave>
 static const void* min_kernel_ptr() {
-    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT>);
+    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT, L>);
 }
 
 template <int POT>
-static const void* minimize_kernel_pot(int mixed, int c, int large) {
+static const void* minimize_kernel_pot(int mixed, int c, int large, bool small16) {
+    if (c == 0 && small16)  // every cluster of the class has at most 16 atoms
+        return mixed ? min_kernel_ptr<1, 1, 1, true, POT, 16>()
+                     : min_kernel_ptr<0, 1, 1, true, POT, 16>();
     if (c < 3) {
         switch (c * 2 + (mixed ? 1 : 0)) {
             case 0: return min_kernel_ptr<0, 1, 1, true, POT>();
@@ -882,9 +885,9 @@ static const void* minimize_kernel_pot(int mixed, int c, int large) {
     return nullptr;
 }
 
-const void* minimize_kernel_for(int mixed, int pot, int c, int large) {
-    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large)
-                             : minimize_kernel_pot<kPairLJ>(mixed, c, large);
+const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool small16) {
+    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large, small16)
+                             : minimize_kernel_pot<kPairLJ>(mixed, c, large, small16);
 }
 
 int class_block(int c, int large) { return kWave * shape_of(c, large).W; }
@@ -896,9 +899,9 @@ hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_minimize_class(int mixed, int c, int large, int grid, const MinArgs& a,
-                                 hipStream_t st) {
-    const void* k = minimize_kernel_for(mixed, a.pot, c, large);
+hipError_t launch_minimize_class(int mixed, int c, int large, bool small16, int grid,
+                                 const MinArgs& a, hipStream_t st) {
+    const void* k = minimize_kernel_for(mixed, a.pot, c, large, small16);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {const_cast<MinArgs*>(&a)};
     return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large)), args, 0, st);

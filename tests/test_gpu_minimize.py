@@ -54,6 +54,32 @@ def test_fp64_bitwise_per_class(cls):
     assert np.all(r["status"] == lj.CONVERGED)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_small_clusters_16_lane_reductions(prec):
+    """Batches whose clusters all have at most 16 atoms run the minimiser with
+    16-leaf reductions (one 16-lane row, then broadcast).  The same clusters
+    in a batch that also holds a 17-atom cluster run with 64-lane reductions:
+    every output is bit-identical between the two, and the FP64 path is
+    bit-identical to the oracle (whose tree pads N <= 16 to 16 leaves)."""
+    sizes = list(range(0, 17)) + [13] * 24
+    off, x = random_starts(sizes, 4242)
+    p = lj.lbfgs_params()
+    announce(f"minimize {prec} small16 sizes={len(sizes)} clusters <= 16 atoms")
+    b, xd = to_dev(off, x)
+    r = host_dict(lj.minimize(b, xd, p, prec))
+    off2, x2 = random_starts(sizes + [17], 4242)
+    assert np.array_equal(x2[:, :off[-1]], x)  # the same starts, one more cluster
+    b2, xd2 = to_dev(off2, x2)
+    r2 = host_dict(lj.minimize(b2, xd2, p, prec))
+    n = len(sizes)
+    for k in KEYS:
+        a2 = r2[k][:, :off[-1]] if k == "xyz" else r2[k][:n]
+        assert np.array_equal(r[k], a2), k
+    if prec == "fp64":
+        assert_same(r, O.minimize(off, x, oracle_params(p)))
+    assert np.all(r["status"] == lj.CONVERGED)
+
+
 def test_fp64_iteration_cap_large_cluster():
     off, x = random_starts([1000, 600], 31)
     p = lj.lbfgs_params(max_iter=25)
