@@ -487,13 +487,15 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 //     distance 32 on lanes 0-31 only (every pair of the tile once), with the
 //     rotating reaction accumulator below and a final exchange of halves;
 //   - round t = 1 .. nt/2: tile tau pairs with tile J = tau + t (mod nt), every
-//     pair once; for even nt the last round runs on tau < nt/2 only.  The
-//     reaction on J's atom (l + k) accumulates in a register that is rotated
-//     one lane per step (DPP wave_rol:1, folded into the add) so that after
-//     64 steps lane l holds the reaction on J's atom l; it goes to the LDS
-//     buffer of the round, and after the round's barrier the owner of J adds
-//     it.  In a round every tile is the partner of at most one tile, so no
-//     two writers meet (no atomics) and all sums have a fixed order.
+//     pair once; for even nt the last round meets each tile pair from both
+//     sides, so each side takes half of the 64 ring distances.  The reaction
+//     on J's atom (l + k) accumulates in a register that is rotated one lane
+//     per step (DPP wave_rol:1, folded into the add), so after the last
+//     distance k lane l holds the reaction on J's atom (l + k) mod 64; it goes
+//     to that atom's slot of the round's LDS buffer, and after the round's
+//     barrier the owner of J adds it.  In a round every tile is the partner of
+//     exactly one tile, so no two writers meet (no atomics) and all sums have a
+//     fixed order.
 // Atoms n .. 64 nt - 1 are padding placed 1e8 apart on the x axis: their
 // pair terms underflow to exactly zero.  FP32 partial sums cover one tile
 // pair (at most 64 terms) and are added into FP64.  e_i is returned in the
@@ -524,14 +526,18 @@ __device__ __forceinline__ float4 tile_pad(int i) {
     return make_float4(kPadSpacing * (float)(1 + (i & 63)), 0.0f, 0.0f, 0.0f);
 }
 
-// Unique pairs of tile (pi: this lane's atom) with tile pj (base: partner
-// tile's doubled copy); returns the reaction on partner atom `lane`.
+// Pairs of this lane's atom pi with partner-tile atoms (lane + k) mod 64 for
+// k = k_begin .. k_begin + NSTEPS - 1 (base: the partner tile's doubled copy).
+// Returns the reaction register, which then holds the reaction on partner
+// atom (lane + k_begin + NSTEPS - 1) mod 64.
+template <int NSTEPS>
 __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __restrict__ base,
-                                            int lane, float& te, float& tx, float& ty, float& tz) {
+                                            int lane, int k_begin, float& te, float& tx,
+                                            float& ty, float& tz) {
     float rx = 0.0f, ry = 0.0f, rz = 0.0f;
     const float4* src = base + lane;
 #pragma unroll 1
-    for (int k0 = 0; k0 < kWave; k0 += kGroup32) {
+    for (int k0 = k_begin; k0 < k_begin + NSTEPS; k0 += kGroup32) {
         float4 p[kGroup32];
 #pragma unroll
         for (int u = 0; u < kGroup32; ++u) p[u] = src[k0 + u];
@@ -549,13 +555,13 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
             ty = fmaf(f, dy, ty);
             tz = fmaf(f, dz, tz);
             // lane l's accumulator moves to lane l - 1 before each step, so it
-            // follows partner atom l + k (at k = 0 it rotates zeros)
+            // follows partner atom l + k (at the first step it rotates zeros)
             rx = rol1(rx) - f * dx;
             ry = rol1(ry) - f * dy;
             rz = rol1(rz) - f * dz;
         }
     }
-    return make_float3(rol1(rx), rol1(ry), rol1(rz));
+    return make_float3(rx, ry, rz);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,30 +734,44 @@ __device__ __forceinline__ void pairs_tiles(int n, const float4* __restrict__ po
     }
     const int rounds = nt / 2;
     for (int t = 1; t <= rounds; ++t) {
+        // For even nt the last round meets every tile pair from both sides:
+        // tile tau < nt/2 takes ring distances 0 .. 31 towards its partner and
+        // the partner takes distances 1 .. 32 back (distances 32 .. 63 seen
+        // from tau), so both halves of the team work 32 steps.
         const bool half = (nt % 2 == 0) && t == rounds;
         float* rb = rbuf + (t & 1) * 3 * S;
 #pragma unroll
         for (int a = 0; a < A; ++a) {
             const int tau = a * W + w;
-            if (tau >= nt || (half && tau >= rounds)) continue;
+            if (tau >= nt) continue;
             int J = tau + t;
             if (J >= nt) J -= nt;
             const float4 pi = pos[128 * tau + lane];
             float te = 0.0f, tx = 0.0f, ty = 0.0f, tz = 0.0f;
-            const float3 r = tile_pair(pi, pos + 128 * J, lane, te, tx, ty, tz);
+            float3 r;
+            int k_last;
+            if (half) {
+                const int k_begin = tau < rounds ? 0 : 1;
+                r = tile_pair<kWave / 2>(pi, pos + 128 * J, lane, k_begin, te, tx, ty, tz);
+                k_last = k_begin + kWave / 2 - 1;
+            } else {
+                r = tile_pair<kWave>(pi, pos + 128 * J, lane, 0, te, tx, ty, tz);
+                k_last = kWave - 1;
+            }
             e[a] += 2.0 * (double)te;
             g[0][a] += (double)tx;
             g[1][a] += (double)ty;
             g[2][a] += (double)tz;
-            rb[64 * J + lane] = r.x;
-            rb[S + 64 * J + lane] = r.y;
-            rb[2 * S + 64 * J + lane] = r.z;
+            const int d = (lane + k_last) & (kWave - 1);  // the partner atom of the reaction
+            rb[64 * J + d] = r.x;
+            rb[S + 64 * J + d] = r.y;
+            rb[2 * S + 64 * J + d] = r.z;
         }
         __syncthreads();
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
+        for (int a = 0; a < A; ++a) {  // every tile is the partner of exactly one tile
             const int tau = a * W + w;
-            if (tau >= nt || (half && tau < rounds)) continue;  // no partner wrote to tau
+            if (tau >= nt) continue;
             g[0][a] += (double)rb[64 * tau + lane];
             g[1][a] += (double)rb[S + 64 * tau + lane];
             g[2][a] += (double)rb[2 * S + 64 * tau + lane];
