@@ -141,7 +141,7 @@ struct MinLayout {
     size_t list = 0, cls = 0, queue = 0, hist = 0, total = 0;
     int top_class = -1;
     int large = 0;
-    bool small16 = false;  // every cluster has at most 16 atoms
+    bool narrow[lj::kNumClasses] = {false, false, false, false};  // see minimize_kernel_for
     int grid[lj::kNumClasses] = {0, 0, 0, 0};
 };
 
@@ -158,12 +158,14 @@ lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int l
     L.queue = off;
     off = align_up(off + sizeof(int32_t) * lj::kNumClasses);
     L.top_class = lj::class_of(max_n < 0 ? 0 : max_n);
-    L.small16 = max_n <= 16;  // the plan rejects clusters above max_n
+    // the plan rejects clusters above max_n, so max_n bounds every class
+    L.narrow[0] = max_n <= 16;
+    L.narrow[2] = max_n <= 192;
     auto grid_for = [&](int c, int large_shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, lj::minimize_kernel_for(mixed, pot, c, large_shape, L.small16),
-            lj::class_block(c, large_shape), 0));
+            &per_cu, lj::minimize_kernel_for(mixed, pot, c, large_shape, L.narrow[c]),
+            lj::class_block(c, large_shape, L.narrow[c]), 0));
         if (per_cu < 1) per_cu = 1;
         long g = (long)per_cu * di.cus;
         if (g > num) g = num;
@@ -250,7 +252,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     if (L.top_class == 0) {
         a.cls = 0;
         a.hist = nullptr;
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, 0, L.large, L.small16, L.grid[0], a, st));
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, 0, L.large, L.narrow[0], L.grid[0], a, st));
         return LJ_OK;
     }
     // several size classes: run them concurrently on side streams
@@ -263,7 +265,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
         a.cls = c;
         a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
         LJ_HIP_TRY(hipStreamWaitEvent(ss->s[c], ss->fork, 0));
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.small16, L.grid[c], a,
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.narrow[c], L.grid[c], a,
                                              ss->s[c]));
         LJ_HIP_TRY(hipEventRecord(ss->join[c], ss->s[c]));
     }

@@ -181,6 +181,23 @@ __device__ __forceinline__ double tree(const double* r) {
     }
 }
 
+// Balanced tree over the W wavefront sums of a team, padded with zeros to a
+// power of two (a team of 3 wavefronts adds its third sum to a zero, as the
+// pairwise sum over the atom index padded to 256 does).
+template <int W>
+__device__ __forceinline__ double tree_w(const double* r) {
+    if constexpr ((W & (W - 1)) == 0) {
+        return tree<W>(r);
+    } else {
+        constexpr int P = W < 2 ? 1 : W < 4 ? 4 : W < 8 ? 8 : 16;
+        static_assert(W < P && P <= 16, "teams of at most 16 wavefronts");
+        double q[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) q[k] = k < W ? r[k] : 0.0;
+        return tree<P>(q);
+    }
+}
+
 // Team reduction scratch in LDS: two alternating banks of NV x W doubles.
 // One barrier per reduction: a bank is rewritten only two reductions later,
 // and every thread has passed the intermediate reduction's barrier (after
@@ -238,7 +255,7 @@ __device__ __forceinline__ void team_sum(double (&vals)[NV][A], double (&out)[NV
                 double rw[W];
 #pragma unroll
                 for (int q = 0; q < W; ++q) rw[q] = sc.v[bank][k * A + a][q];
-                r[a] = tree<W>(rw);
+                r[a] = tree_w<W>(rw);
             }
             out[k] = uniform(tree<A>(r));  // identical in every lane
         }

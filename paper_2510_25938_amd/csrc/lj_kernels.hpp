@@ -63,14 +63,15 @@ hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const in
                               int64_t total, const double* xyz, double* e, double* g, double rho,
                               hipStream_t st);
 int class_of(int n);
-int class_block(int c, int large);
+int class_block(int c, int large, bool narrow);
 size_t class_hist_bytes_per_wg(int c, int large);
-// small16: the class-0 kernel for batches whose clusters all have at most 16
-// atoms (its reductions run over one 16-lane row).
-const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool small16);
+// narrow: every cluster of class c lies in the lower part of the class's size
+// range (class 0: at most 16 atoms, reductions over one 16-lane row; class 2:
+// at most 192 atoms, three wavefronts).
+const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool narrow);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);
-hipError_t launch_minimize_class(int mixed, int c, int large, bool small16, int grid,
+hipError_t launch_minimize_class(int mixed, int c, int large, bool narrow, int grid,
                                  const MinArgs& a, hipStream_t st);
 
 struct BhDev {

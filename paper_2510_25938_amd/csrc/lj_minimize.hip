@@ -101,7 +101,7 @@ struct Team {
                 double rw[W];
 #pragma unroll
                 for (int q = 0; q < W; ++q) rw[q] = sc->v[bank][a][q];
-                r[a] = tree<W>(rw);
+                r[a] = tree_w<W>(rw);
             }
             double mx = sc->v[bank][A][0];
 #pragma unroll
@@ -830,6 +830,10 @@ hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const in
 // four wavefronts, one atom per lane).  Class 3 (N in 257..1024) keeps it in a
 // global ring and has three interchangeable shapes of 1024 atom slots:
 // 16 wavefronts x 1 atom, 8 x 2, 4 x 4 (chosen by the schedule table).
+// "narrow": every cluster of the class lies in the lower part of its range,
+// so a leaner kernel serves it: class 0 with at most 16 atoms reduces over
+// one 16-lane row, class 2 with at most 192 atoms (three 64-atom tiles) runs
+// three wavefronts instead of four, leaving a SIMD free for other work.
 struct ClassShape {
     int W, A;
     bool hreg;
@@ -838,7 +842,8 @@ constexpr ClassShape kClassShape[kNumClasses] = {{1, 1, true}, {2, 1, true}, {4,
                                                  {16, 1, false}};
 constexpr ClassShape kLargeShape[kNumLargeShapes] = {{16, 1, false}, {8, 2, false}, {4, 4, false}};
 
-static ClassShape shape_of(int c, int large) {
+static ClassShape shape_of(int c, int large, bool narrow) {
+    if (c == 2 && narrow) return {3, 1, true};
     return c == 3 ? kLargeShape[large] : kClassShape[c];
 }
 
@@ -849,7 +854,7 @@ int class_of(int n) {
 }
 
 size_t class_hist_bytes_per_wg(int c, int large) {
-    const ClassShape s = shape_of(c, large);
+    const ClassShape s = shape_of(c, large, false);
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
@@ -859,10 +864,12 @@ static const void* min_kernel_ptr() {
 }
 
 template <int POT>
-static const void* minimize_kernel_pot(int mixed, int c, int large, bool small16) {
-    if (c == 0 && small16)  // every cluster of the class has at most 16 atoms
+static const void* minimize_kernel_pot(int mixed, int c, int large, bool narrow) {
+    if (c == 0 && narrow)  // every cluster of the class has at most 16 atoms
         return mixed ? min_kernel_ptr<1, 1, 1, true, POT, 16>()
                      : min_kernel_ptr<0, 1, 1, true, POT, 16>();
+    if (c == 2 && narrow)  // every cluster of the class has at most 192 atoms
+        return mixed ? min_kernel_ptr<1, 3, 1, true, POT>() : min_kernel_ptr<0, 3, 1, true, POT>();
     if (c < 3) {
         switch (c * 2 + (mixed ? 1 : 0)) {
             case 0: return min_kernel_ptr<0, 1, 1, true, POT>();
@@ -885,12 +892,12 @@ static const void* minimize_kernel_pot(int mixed, int c, int large, bool small16
     return nullptr;
 }
 
-const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool small16) {
-    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large, small16)
-                             : minimize_kernel_pot<kPairLJ>(mixed, c, large, small16);
+const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool narrow) {
+    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large, narrow)
+                             : minimize_kernel_pot<kPairLJ>(mixed, c, large, narrow);
 }
 
-int class_block(int c, int large) { return kWave * shape_of(c, large).W; }
+int class_block(int c, int large, bool narrow) { return kWave * shape_of(c, large, narrow).W; }
 
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st) {
@@ -899,12 +906,12 @@ hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_minimize_class(int mixed, int c, int large, bool small16, int grid,
+hipError_t launch_minimize_class(int mixed, int c, int large, bool narrow, int grid,
                                  const MinArgs& a, hipStream_t st) {
-    const void* k = minimize_kernel_for(mixed, a.pot, c, large, small16);
+    const void* k = minimize_kernel_for(mixed, a.pot, c, large, narrow);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {const_cast<MinArgs*>(&a)};
-    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large)), args, 0, st);
+    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large, narrow)), args, 0, st);
 }
 
 }  // namespace lj

@@ -54,20 +54,29 @@ def test_fp64_bitwise_per_class(cls):
     assert np.all(r["status"] == lj.CONVERGED)
 
 
+NARROW = {
+    # class 0 with at most 16 atoms: reductions over one 16-lane row
+    "c0_16": (list(range(0, 17)) + [13] * 24, 17),
+    # class 2 with at most 192 atoms: three wavefronts (three 64-atom tiles)
+    "c2_192": ([129, 150, 192, 13, 100, 160, 129, 185], 193),
+}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_small_clusters_16_lane_reductions(prec):
-    """Batches whose clusters all have at most 16 atoms run the minimiser with
-    16-leaf reductions (one 16-lane row, then broadcast).  The same clusters
-    in a batch that also holds a 17-atom cluster run with 64-lane reductions:
-    every output is bit-identical between the two, and the FP64 path is
-    bit-identical to the oracle (whose tree pads N <= 16 to 16 leaves)."""
-    sizes = list(range(0, 17)) + [13] * 24
+@pytest.mark.parametrize("case", list(NARROW))
+def test_narrow_class_kernels(case, prec):
+    """When max_n keeps a size class in the lower part of its range, a leaner
+    kernel serves it (16-lane reductions for N <= 16; three wavefronts for
+    129 <= N <= 192).  The same clusters in a batch that also holds one larger
+    cluster run the full kernels: every output is bit-identical between the
+    two, and the FP64 path is bit-identical to the oracle."""
+    sizes, extra = NARROW[case]
     off, x = random_starts(sizes, 4242)
     p = lj.lbfgs_params()
-    announce(f"minimize {prec} small16 sizes={len(sizes)} clusters <= 16 atoms")
+    announce(f"minimize {prec} narrow {case} sizes={sizes[:12]}... extra={extra}")
     b, xd = to_dev(off, x)
     r = host_dict(lj.minimize(b, xd, p, prec))
-    off2, x2 = random_starts(sizes + [17], 4242)
+    off2, x2 = random_starts(sizes + [extra], 4242)
     assert np.array_equal(x2[:, :off[-1]], x)  # the same starts, one more cluster
     b2, xd2 = to_dev(off2, x2)
     r2 = host_dict(lj.minimize(b2, xd2, p, prec))
