@@ -321,8 +321,26 @@ __device__ __forceinline__ double exp_cw(double z) {
 // s6 = q^3, and g_i = sum_{j != i} q s6 (24 - 48 s6) (x_i - x_j).
 // ---------------------------------------------------------------------------
 
+// 1/x for 2^-767 <= x < 2^1022 with the operations of the IEEE division
+// 1.0 / x that survive in that range: the hardware reciprocal estimate, two
+// Newton steps y <- y + y (1 - x y), and the final correction
+// q = y + y (1 - x y).  There the division's operand scaling (v_div_scale) is
+// the identity and its special-case fix-up (v_div_fixup) returns q unchanged,
+// so q is the same correctly rounded quotient.  For smaller x the pair term
+// s6 = q^3 overflows in both forms (the energy is not finite) and for larger x
+// both give s6 = 0; a non-finite energy is recomputed with the IEEE division.
+__device__ __forceinline__ double recip_in_range(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(fma(-x, y, 1.0), y, y);
+}
+
 // One ordered pair (i = slot a of this thread, partner j at p), FP64.  The
-// self pair (r2 = 0) gets q = 0, so it adds exactly zero.
+// self pair (r2 = 0) gets q = 0, so it adds exactly zero.  IEEE: q = 1 / r2 by
+// the full division; otherwise recip_in_range (the same bits wherever the
+// cluster's energy is finite).
+template <bool IEEE>
 __device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi, double yi,
                                           double zi, double& e, double& gx, double& gy,
                                           double& gz) {
@@ -330,7 +348,7 @@ __device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi,
     const double dy = yi - p.y;
     const double dz = zi - p.z;
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const double q = self ? 0.0 : 1.0 / r2;
+    const double q = self ? 0.0 : (IEEE ? 1.0 / r2 : recip_in_range(r2));
     const double s6 = (q * q) * q;
     e = e + fma(s6, s6, -s6);
     const double f = (q * s6) * fma(-48.0, s6, 24.0);
@@ -404,7 +422,7 @@ __device__ __forceinline__ void pair_morse32(const float4 p, bool self, float xi
 constexpr int kGroup64 = 4;
 constexpr int kGroup32 = 8;
 
-template <int A, int T, int POT>
+template <int A, int T, int POT, bool IEEE = true>
 __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ pos,
                                            const double (&x)[3][A], double (&e)[A],
                                            double (&g)[3][A], double rho) {
@@ -415,7 +433,8 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
             pair_morse64(p, self, x[0][a], x[1][a], x[2][a], rho, c, e[a], g[0][a], g[1][a],
                          g[2][a]);
         else
-            pair_fp64(p, self, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a], g[2][a]);
+            pair_fp64<IEEE>(p, self, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a],
+                            g[2][a]);
     };
 #pragma unroll
     for (int a = 0; a < A; ++a) {

@@ -158,12 +158,24 @@ struct Team {
         } else if constexpr (F32) {
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
         } else {
-            pairs_fp64<A, T, POT>(n, pos64, x, e[0], g, rho);
+            pairs_fp64<A, T, POT, POT == kPairMorse>(n, pos64, x, e[0], g, rho);
         }
 #pragma unroll
         for (int a = 0; a < A; ++a)
             if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
         team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
+        if constexpr (!F32 && POT == kPairLJ) {
+            // only a pair distance outside the range of recip_in_range can make
+            // 1/r2 differ from the IEEE quotient, and it makes E not finite:
+            // then the evaluation is repeated with the IEEE division
+            if (!isfinite(o[0])) {
+                pairs_fp64<A, T, POT, true>(n, pos64, x, e[0], g, rho);
+#pragma unroll
+                for (int a = 0; a < A; ++a)
+                    if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
+                team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
+            }
+        }
         return (POT == kPairMorse ? 0.5 : 2.0) * o[0];
     }
 };
