@@ -78,6 +78,38 @@ def test_coincident_atoms_nonfinite():
         assert not np.isfinite(host(E)[0])
 
 
+EXTREME = {"coincident": 0.0, "1e-120": 1e-120, "1e-160": 1e-160, "1e154": 1e154,
+           "1e200": 1e200}
+
+
+def test_fp64_extreme_distances_bitwise():
+    """Pair distances outside the range where the FP64 loop's 1/r2 skips the
+    general division's scaling and fix-up (r2 < 2^-767: coincident, 1e-120,
+    a subnormal r2; r2 >= 2^1022: 1e154, and an r2 that overflows to inf).
+    Energies and gradients, NaN and signed infinities included, equal the
+    oracle's IEEE results: a non-finite energy triggers the recomputation with
+    the full division, and above the range both forms give zero pair terms."""
+    xs = []
+    for d in EXTREME.values():
+        c = np.zeros((3, 4))
+        c[0] = [0.0, d, 2.0, 3.5]
+        c[1] = [0.0, 0.0, 0.3, -0.2]
+        xs.append(c)
+    off = np.arange(0, 4 * len(xs) + 1, 4).astype(np.int32)
+    x = np.concatenate(xs, axis=1)
+    announce(f"eval fp64 extreme distances {list(EXTREME)}")
+    b, xd = to_dev(off, x)
+    E, g = lj.energy_grad(b, xd, "fp64")
+    Eo, go = O.energy_grad(off, x)
+    assert np.array_equal(host(E), Eo, equal_nan=True)
+    assert np.array_equal(host(g), go, equal_nan=True)
+    r = {k: v.cpu().numpy() for k, v in lj.minimize(b, xd, lj.lbfgs_params(), "fp64").items()
+         if v is not None}
+    ro = O.minimize(off, x)
+    for k in ("energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k], equal_nan=True), k
+
+
 def test_offsets_above_max_n_are_rejected_per_cluster():
     off, x = random_starts([10, 70, 10], 6)
     announce("eval offsets above max_n")
