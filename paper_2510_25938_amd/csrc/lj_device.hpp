@@ -342,8 +342,8 @@ __device__ __forceinline__ double recip_in_range(double x) {
 // cluster's energy is finite).
 template <bool IEEE>
 __device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi, double yi,
-                                          double zi, double& e, double& gx, double& gy,
-                                          double& gz) {
+                                          double zi, double k24, double km48, double& e,
+                                          double& gx, double& gy, double& gz) {
     const double dx = xi - p.x;
     const double dy = yi - p.y;
     const double dz = zi - p.z;
@@ -351,7 +351,7 @@ __device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi,
     const double q = self ? 0.0 : (IEEE ? 1.0 / r2 : recip_in_range(r2));
     const double s6 = (q * q) * q;
     e = e + fma(s6, s6, -s6);
-    const double f = (q * s6) * fma(-48.0, s6, 24.0);
+    const double f = (q * s6) * fma(km48, s6, k24);  // k24 = 24, km48 = -48
     gx = fma(f, dx, gx);
     gy = fma(f, dy, gy);
     gz = fma(f, dz, gz);
@@ -428,13 +428,18 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
                                            double (&g)[3][A], double rho) {
     const int t = threadIdx.x;
     const double c = -2.0 * rho;
+    // 24 and -48 held in registers for the whole loop: a 64-bit constant that
+    // is not an inline one would otherwise be rebuilt by two moves per pair
+    double k24 = 24.0, km48 = -48.0;
+    asm volatile("" : "+v"(k24));
+    asm volatile("" : "+s"(km48));
     auto pair = [&](const double4 p, bool self, int a) {
         if constexpr (POT == kPairMorse)
             pair_morse64(p, self, x[0][a], x[1][a], x[2][a], rho, c, e[a], g[0][a], g[1][a],
                          g[2][a]);
         else
-            pair_fp64<IEEE>(p, self, x[0][a], x[1][a], x[2][a], e[a], g[0][a], g[1][a],
-                            g[2][a]);
+            pair_fp64<IEEE>(p, self, x[0][a], x[1][a], x[2][a], k24, km48, e[a], g[0][a],
+                            g[1][a], g[2][a]);
     };
 #pragma unroll
     for (int a = 0; a < A; ++a) {

@@ -71,8 +71,11 @@ struct Team {
 
     // u.v and the largest per-atom squared norm of v, with the same values as
     // dot() and max_atom_norm2() but one exchange between the wavefronts.
+    // vmax2 is exact whenever it exceeds cap2; otherwise it is some value
+    // <= cap2 (one wavefront: a ballot over the lanes skips the max when no
+    // atom exceeds cap2).
     __device__ __forceinline__ void dot_max(const double (&u)[3][A], const double (&v)[3][A],
-                                            double& uv, double& vmax2) {
+                                            double& uv, double& vmax2, double cap2) {
         double p[A], m = 0.0;
         double ws[A];
 #pragma unroll
@@ -83,11 +86,11 @@ struct Team {
         }
 #pragma unroll
         for (int a = 0; a < A; ++a) ws[a] = wave_sum<L>(p[a]);
-        m = wave_max<L>(m);
         if constexpr (W == 1) {
             uv = tree<A>(ws);
-            vmax2 = m;
+            vmax2 = __builtin_amdgcn_ballot_w64(m > cap2) != 0 ? wave_max<L>(m) : 0.0;
         } else {
+            m = wave_max<L>(m);
             const int w = threadIdx.x / kWave;
             if (threadIdx.x % kWave == 0) {
 #pragma unroll
@@ -451,14 +454,14 @@ __device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double 
 #pragma unroll
             for (int a = 0; a < A; ++a) d[c][a] = -d[c][a];
         double gd, dmax2;
-        tm.dot_max(g, d, gd, dmax2);
+        tm.dot_max(g, d, gd, dmax2, ms2);
         if (uniform(H.hist) > 0 && !(gd < 0.0)) {
             H.clear();
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int a = 0; a < A; ++a) d[c][a] = -g[c][a];
-            tm.dot_max(g, d, gd, dmax2);
+            tm.dot_max(g, d, gd, dmax2, ms2);
         }
         if (dmax2 > ms2) {
             const double sc = p.max_step / sqrt(dmax2);
