@@ -337,7 +337,7 @@ __device__ __forceinline__ double recip_in_range(double x) {
 }
 
 // One ordered pair (i = slot a of this thread, partner j at p), FP64.  The
-// self pair (r2 = 0) gets q = 0, so it adds exactly zero.  IEEE: q = 1 / r2 by
+// self pair (r2 = 0) adds exactly zero.  IEEE: q = 1 / r2 by
 // the full division; otherwise recip_in_range (the same bits wherever the
 // cluster's energy is finite).
 template <bool IEEE>
@@ -348,7 +348,13 @@ __device__ __forceinline__ void pair_fp64(const double4 p, bool self, double xi,
     const double dy = yi - p.y;
     const double dz = zi - p.z;
     const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const double q = self ? 0.0 : (IEEE ? 1.0 / r2 : recip_in_range(r2));
+    // the self pair (r2 = 0) clears the high word of q: q is then zero or
+    // subnormal, s6 = q^3 is exactly 0 and the pair adds exact zeros (one
+    // select instead of two)
+    double q = IEEE ? 1.0 / r2 : recip_in_range(r2);
+    int2 qb = *reinterpret_cast<int2*>(&q);
+    qb.y = self ? 0 : qb.y;
+    q = *reinterpret_cast<double*>(&qb);
     const double s6 = (q * q) * q;
     e = e + fma(s6, s6, -s6);
     const double f = (q * s6) * fma(km48, s6, k24);  // k24 = 24, km48 = -48
@@ -547,7 +553,8 @@ template <int W, int A>
 constexpr bool kUseTiles = W * A * kWave <= 2048;
 
 // A tile evaluates 32 ring distances per atom within itself, against n
-// partners per atom in the ordered loop: the tiles win above n = 32.
+// partners per atom in the ordered loop: the tiles win above n = 32 (where a
+// one-wavefront cluster of at most 41 atoms takes the ring instead).
 __device__ __forceinline__ bool tiles_for(int n) { return n > kWave / 2; }
 
 constexpr float kPadSpacing = 1.0e8f;

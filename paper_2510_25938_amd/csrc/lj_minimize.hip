@@ -10,7 +10,8 @@
 // loop, all reductions go through wavefront butterflies and (for W > 1) a
 // small LDS exchange, and for N <= 256 the m (s, y) history pairs stay in
 // registers.  Teams are persistent: they claim clusters from a queue that
-// lists the batch by N descending (longest first), one launch per size class.
+// lists the batch by N descending (longest first), one launch per size class
+// (the size classes run concurrently on side streams).
 #include <hip/hip_runtime.h>
 
 #include "lj_kernels.hpp"
@@ -115,10 +116,14 @@ struct Team {
         }
     }
 
-    // E and g at x.  F32: FP32 pair arithmetic and tile sums, FP64 totals.
-    // Ordered pairs count each pair twice: E = 2 sum_i e_i for Eq. (1)
-    // (e_i holds r^-12 - r^-6, a quarter of the pair energy) and
-    // E = 0.5 sum_i e_i for the Morse pair (e_i holds V).
+    // E and g at x.  FP64: the ordered-pair loop in the oracle's order.
+    // F32: FP32 pair arithmetic and per-atom FP32 partial sums, FP64 totals;
+    // the unique-pair ring for one-wavefront clusters of 20 to 41 atoms, the
+    // unique-pair 64-atom tiles above 32 atoms otherwise (Eq. (1)), else the
+    // ordered loop.  Every loop reports e_i in the ordered-pair convention,
+    // which counts each pair twice: E = 2 sum_i e_i for Eq. (1) (e_i holds
+    // r^-12 - r^-6, a quarter of the pair energy) and E = 0.5 sum_i e_i for
+    // the Morse pair (e_i holds V).
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
         constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
