@@ -25,7 +25,7 @@ from paper_2510_25938_amd.inputs import random_starts
 pytestmark = pytest.mark.gpu
 
 SHAPES = {
-    "w1": ([0, 1, 2, 3, 13, 38, 63, 64], 6.0),
+    "w1": ([0, 1, 2, 3, 13, 38, 39, 40, 41, 63, 64], 6.0),
     "w2": ([65, 5, 100, 128], 3.0),
     "w4": ([129, 150, 200, 256], 14.0),
     "w8": ([257, 300, 512], 6.0),
