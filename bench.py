@@ -362,12 +362,22 @@ def main():
     if not args.no_cpu:
         from oracle import oracle as O
 
-        t0 = time.perf_counter()
-        ro = O.minimize(off, x)
-        cpu_s = time.perf_counter() - t0
+        # one thread pinned to one host core for the oracle leg, then restored
+        aff = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+        core = min(aff) if aff else None
+        if core is not None:
+            os.sched_setaffinity(0, {core})
+        try:
+            t0 = time.perf_counter()
+            ro = O.minimize(off, x)
+            cpu_s = time.perf_counter() - t0
+        finally:
+            if aff:
+                os.sched_setaffinity(0, aff)
         cpu = {"value": B / cpu_s, "unit": "minimisations/s", "cores": 1, "kind": "oracle",
                "sample": f"all {B} LJ38 starts of the workload, FP64 L-BFGS, one host thread "
-                         f"({cpu_s:.2f} s)", "cpu_model": cpu_model()}
+                         f"pinned to core {core} ({cpu_s:.2f} s)", "cpu_model": cpu_model(),
+               "host_cores": len(aff) if aff else os.cpu_count()}
         cpu["pool"] = oracle_pool(O, off, x, ro)
         h64, hm = fp64["host"], mixed["host"]
         parity["fp64_bitwise_frac"] = float(np.mean(
