@@ -9,7 +9,11 @@
  *     structs whose pointer members are device pointers unless noted.
  *   - `stream` is a hipStream_t passed as void*.  Every call only enqueues
  *     work on that stream and returns; results are valid once the stream has
- *     been synchronised.  No call synchronises the host.
+ *     been synchronised.  No call synchronises the host, except
+ *     lj_autotune, which times launches.
+ *   - Host threads may call concurrently when each uses its own stream and
+ *     workspace: the side streams that run size classes concurrently and the
+ *     cached step graphs are kept per (device, caller stream).
  *   - No call allocates device memory.  Scratch memory is a caller-provided
  *     workspace whose size comes from the matching *_workspace_bytes query;
  *     the workspace must stay untouched until the enqueued work completes.

@@ -192,10 +192,13 @@ lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int l
     return LJ_OK;
 }
 
-// Per-device side streams (default priority) and events used to run the
-// minimiser's size classes concurrently: fork from the caller's stream after
-// the plan kernel, one class per side stream, join back before returning.
-// The pattern is also valid under stream capture (parallel graph branches).
+// Side streams (default priority) and events used to run the minimiser's size
+// classes concurrently: fork from the caller's stream after the plan kernel,
+// one class per side stream, join back before returning.  The pattern is also
+// valid under stream capture (parallel graph branches).  Each (device, caller
+// stream) pair has its own set: a side stream pulled into a capture stays in
+// capture mode until the capture ends, so a set shared with callers on other
+// streams would let their eager launches land in that graph.
 struct SideStreams {
     bool ready = false;
     hipStream_t s[lj::kNumClasses];
@@ -204,15 +207,15 @@ struct SideStreams {
     std::mutex mu;
 };
 std::mutex g_side_mu;
-std::vector<SideStreams*> g_side;
+std::map<std::pair<int, hipStream_t>, SideStreams*> g_side;
 
-lj_status side_streams(SideStreams*& out) {
+lj_status side_streams(hipStream_t caller, SideStreams*& out) {
     int dev = 0;
     LJ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_side_mu);
-    if ((int)g_side.size() <= dev) g_side.resize(dev + 1, nullptr);
-    if (!g_side[dev]) g_side[dev] = new SideStreams();  // lives until the process ends
-    SideStreams* ss = g_side[dev];
+    SideStreams*& slot = g_side[{dev, caller}];
+    if (!slot) slot = new SideStreams();  // lives until the process ends
+    SideStreams* ss = slot;
     if (!ss->ready) {
         for (int c = 0; c < lj::kNumClasses; ++c) {
             LJ_HIP_TRY(hipStreamCreateWithFlags(&ss->s[c], hipStreamNonBlocking));
@@ -257,7 +260,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     }
     // several size classes: run them concurrently on side streams
     SideStreams* ss = nullptr;
-    lj_status r = side_streams(ss);
+    lj_status r = side_streams(st, ss);
     if (r != LJ_OK) return r;
     std::lock_guard<std::mutex> lk(ss->mu);
     LJ_HIP_TRY(hipEventRecord(ss->fork, st));
