@@ -5,6 +5,8 @@ row and the final state).  Mixed chains are checked by replay: the oracle's
 selection / Metropolis / adaptation, fed the GPU's candidate energies, takes
 the same decisions bit for bit.  Graph replays equal eager execution.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -136,3 +138,89 @@ def test_mixed_chains_replay(chains, steps):
         gb = go[:, off[c]:off[c + 1]]
         assert np.sqrt(np.sum(gb * gb)) < 1e-5
     assert np.all(tr["accepted"].sum(axis=1) > 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bh_short_workspace_is_rejected(prec):
+    """lj_bh_step with a missing or short workspace returns LJ_E_WORKSPACE and
+    leaves the chain state as it was."""
+    off, b, r, p = start_chains([13, 38], 45)
+    bh = lj.bh_params(cands=4, seed=3)
+    chains = lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, prec)
+    announce(f"short workspace bh_step prec={prec} need={chains.workspace.numel()}")
+    before = [t.clone() for t in (chains.xyz_cur, chains.e_cur, chains.step_size,
+                                  chains.win_accepts, chains.step_index)]
+    L = lj.lib()
+    for ws, nb in ((None, chains.workspace.numel()),
+                   (chains.workspace.data_ptr(), chains.workspace.numel() - 1)):
+        st = L.lj_bh_step(C.byref(b.desc()), C.byref(chains.state), C.byref(bh), C.byref(p),
+                          lj.precision_code(prec), 2, None, ws, nb, None)
+        assert st == lj.E_WORKSPACE
+    torch.cuda.synchronize()
+    after = (chains.xyz_cur, chains.e_cur, chains.step_size, chains.win_accepts,
+             chains.step_index)
+    for a, z in zip(before, after):
+        assert torch.equal(a, z)
+
+
+def test_threads_on_separate_streams_match_serial_runs():
+    """Two host threads, each on its own stream: one steps basin-hopping chains
+    of two size classes (the first step captures its graph), the other runs
+    eager minimisations of three size classes.  Each thread's results equal
+    the same work done alone, bit for bit."""
+    import threading
+
+    off, b, r, p = start_chains([38, 70, 38, 70], 47)
+    bh = lj.bh_params(cands=4, seed=11)
+    moff, mx = random_starts([13, 80, 150, 38], 49)
+    mb, mxd = to_dev(moff, mx)
+    announce("threads: bh_step mixed (38, 70) x 4 steps || minimize fp64 (13, 80, 150, 38) x 6")
+
+    def bh_run(stream):
+        ch = lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "mixed")
+        torch.cuda.synchronize()
+        for _ in range(4):
+            ch.step(1, stream=stream)
+        return ch
+
+    ref_bh = bh_run(None)
+    ref_min = lj.minimize(mb, mxd, p, "fp64")
+    torch.cuda.synchronize()
+
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    chains = lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "mixed")
+    torch.cuda.synchronize()
+    outs, errors = [], []
+
+    def thread_a():
+        try:
+            with torch.cuda.stream(sa):
+                for _ in range(4):
+                    chains.step(1, stream=sa)
+            sa.synchronize()
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    def thread_b():
+        try:
+            with torch.cuda.stream(sb):
+                for _ in range(6):
+                    outs.append(lj.minimize(mb, mxd, p, "fp64", stream=sb))
+            sb.synchronize()
+        except Exception as e:
+            errors.append(e)
+
+    ta, tb = threading.Thread(target=thread_a), threading.Thread(target=thread_b)
+    ta.start()
+    tb.start()
+    ta.join()
+    tb.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for name in ("xyz_cur", "e_cur", "step_size", "win_accepts", "step_index", "e_best_seen",
+                 "e_best_acc", "xyz_best"):
+        assert torch.equal(getattr(chains, name), getattr(ref_bh, name)), name
+    assert len(outs) == 6
+    for o in outs:
+        for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+            assert torch.equal(o[k], ref_min[k]), k

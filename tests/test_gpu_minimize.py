@@ -7,8 +7,11 @@ GPU's recorded switch point reproduces the oracle run from that point bit for
 bit, and every converged result is a minimum to ||g|| < 1e-6 by the oracle's
 own gradient.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
+import torch
 
 from gpu_util import announce, host_dict, to_dev
 from oracle import oracle as O
@@ -192,3 +195,50 @@ def test_mixed_deterministic():
     r2 = host_dict(lj.minimize(b, xd, lj.lbfgs_params(), "mixed"))
     for k in KEYS:
         assert np.array_equal(r1[k], r2[k])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_short_workspace_is_rejected_before_any_work(prec):
+    """A missing or one-byte-short workspace returns LJ_E_WORKSPACE and
+    enqueues nothing: coordinates and outputs keep their values."""
+    off, x = random_starts([13, 38, 80], 41)
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params()
+    nb = lj.minimize_workspace_bytes(b, p, prec)
+    assert nb > 0
+    announce(f"short workspace minimize prec={prec} need={nb}")
+    x0 = xd.clone()
+    for size in (nb - 1, 1):
+        ws = torch.empty(size, dtype=torch.uint8, device=xd.device)
+        with pytest.raises(lj.LJError) as err:
+            lj.minimize(b, xd, p, prec, workspace=ws, inplace=True)
+        assert err.value.args[1] == lj.E_WORKSPACE
+    e = torch.full((b.num,), 7.0, dtype=torch.float64, device=xd.device)
+    i = torch.full((b.num,), -5, dtype=torch.int32, device=xd.device)
+    st = lj.lib().lj_bh_minimize_batch(C.byref(b.desc()), xd.data_ptr(), e.data_ptr(),
+                                       e.data_ptr(), i.data_ptr(), i.data_ptr(), i.data_ptr(),
+                                       None, C.byref(p), lj.precision_code(prec), None, nb, None)
+    assert st == lj.E_WORKSPACE
+    torch.cuda.synchronize()
+    assert torch.equal(xd, x0)
+    assert torch.all(e == 7.0) and torch.all(i == -5)
+    # the exact size is accepted and gives the default path's result
+    ws = torch.empty(nb, dtype=torch.uint8, device=xd.device)
+    r = host_dict(lj.minimize(b, xd, p, prec, workspace=ws))
+    ref = host_dict(lj.minimize(b, xd, p, prec))
+    for k in KEYS:
+        assert np.array_equal(r[k], ref[k]), k
+
+
+def test_autotune_short_workspace_is_rejected():
+    off, x = random_starts([300, 400], 43)
+    b, xd = to_dev(off, x)
+    L = lj.lib()
+    nb = int(L.lj_autotune_workspace_bytes(C.byref(b.desc()), lj.MIXED))
+    assert nb > 0
+    announce(f"short workspace autotune need={nb}")
+    ws = torch.empty(nb - 1, dtype=torch.uint8, device=xd.device)
+    t0, t1 = C.c_float(-2.0), C.c_float(-2.0)
+    st = L.lj_autotune(C.byref(b.desc()), xd.data_ptr(), lj.MIXED, ws.data_ptr(), nb - 1, None,
+                       C.byref(t0), C.byref(t1))
+    assert st == lj.E_WORKSPACE and t0.value == -2.0 and t1.value == -2.0
