@@ -541,6 +541,7 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
     key_add(key, ws);
     key_add(key, ws_bytes);
     key_add(key, st);
+    key_add(key, large_schedule(precision));  // a graph keeps the launch shapes it captured
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -645,9 +646,16 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
     double* g = reinterpret_cast<double*>(w + off);
     off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);
     const int mixed = precision == LJ_MIXED;
-    hipEvent_t e0, e1;
-    LJ_HIP_TRY(hipEventCreate(&e0));
-    LJ_HIP_TRY(hipEventCreate(&e1));
+    struct Events {  // destroyed on every return path
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    LJ_HIP_TRY(hipEventCreate(&evs.e[0]));
+    LJ_HIP_TRY(hipEventCreate(&evs.e[1]));
+    hipEvent_t e0 = evs.e[0], e1 = evs.e[1];
     auto time_it = [&](auto&& launch, float& ms) -> lj_status {
         lj_status r = launch();  // warm-up
         if (r != LJ_OK) return r;
@@ -730,8 +738,6 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
         }
     }
     if (best_min_ms) *best_min_ms = best_min;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     return s;
 }
 
