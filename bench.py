@@ -245,6 +245,32 @@ def workloads(lj, inputs, torch, stream, oracle=None):
     return res
 
 
+def mixed_result_errors(lj, O, batch, starts, params, off, hm, stream, torch):
+    """Error of every mixed-path result against the oracle (untimed).
+
+    The oracle re-evaluates E and ||g|| at each GPU minimum, and polishes in
+    FP64 from each GPU switch point (recorded by one more untimed run, which
+    must reproduce the timed run's results): the GPU polish is expected to
+    equal that run bit for bit."""
+    with torch.cuda.stream(stream):
+        r = lj.minimize(batch, starts, params, "mixed", switch_point=True, stream=stream)
+    stream.synchronize()
+    h = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+    B = len(off) - 1
+    Eo, go = O.energy_grad(off, hm["xyz"])
+    gn = np.array([np.sqrt(np.sum(go[:, off[b]:off[b + 1]] ** 2)) for b in range(B)])
+    ro = O.minimize(off, h["xyz_switch"])
+    same = [np.array_equal(h["xyz"][:, off[b]:off[b + 1]], ro["xyz"][:, off[b]:off[b + 1]])
+            and h["energy"][b] == ro["energy"][b] and h["gnorm"][b] == ro["gnorm"][b]
+            and h["status"][b] == ro["status"][b] for b in range(B)]
+    return {"mixed_rerun_equals_timed": bool(np.array_equal(h["xyz"], hm["xyz"])
+                                             and np.array_equal(h["energy"], hm["energy"])),
+            "mixed_polish_bitwise_frac": float(np.mean(same)),
+            "mixed_energy_abs_err_max_vs_oracle_at_result": float(np.max(np.abs(hm["energy"] - Eo))),
+            "mixed_gnorm_oracle_at_result_max": float(np.max(gn)),
+            "mixed_gnorm_rel_err_max_vs_oracle_at_result": float(np.max(np.abs(hm["gnorm"] - gn) / gn))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +412,7 @@ def main():
         rel = np.abs(hm["energy"] - ro["energy"]) / np.abs(ro["energy"])
         parity["mixed_same_minimum_frac_1e-6"] = float(np.mean(rel <= 1e-6))
         parity["mixed_energy_rel_err_median"] = float(np.median(rel))
+        parity.update(mixed_result_errors(lj, O, batch, starts, params, off, hm, stream, torch))
 
     # Standalone pair kernel: 256 clusters of N = 1000.
     pair = None if args.no_pair else pair_kernel(lj, large_clusters, dev, stream, torch)
