@@ -154,11 +154,30 @@ def timed(torch, stream, fn, reps=1):
     return e0.elapsed_time(e1) / reps, out
 
 
-def workloads(lj, inputs, torch, stream, oracle=None):
-    """Every benchmark workload at full size (beside the headline LJ38 batch)."""
+WORKLOADS = ("lj13bh", "uneven", "large", "morse", "chains")
+
+
+def workloads(lj, inputs, torch, stream, oracle=None, only=None):
+    """Every benchmark workload at full size (beside the headline LJ38 batch);
+    `only`, one of WORKLOADS, runs a single one (for profiler runs)."""
     res = {}
+    if only in (None, "lj13bh"):
+        res.update(lj13_chain(lj, inputs, torch, stream, oracle))
+    for key, w, params in (("uneven", inputs.uneven_batch(), lj.lbfgs_params()),
+                           ("large", inputs.large_clusters(),
+                            lj.lbfgs_params(max_iter=500, polish=0))):
+        if only in (None, key):
+            res.update(one_call(lj, w, params, torch, stream))
+    if only in (None, "morse"):
+        res.update(morse_batch(lj, inputs, torch, stream, oracle))
+    if only in (None, "chains"):
+        res.update(many_chains(lj, inputs, torch, stream))
+    return res
+
+
+def lj13_chain(lj, inputs, torch, stream, oracle):
+    """LJ13 basin hopping: 1 chain x 8 candidates x 200 steps, FP64, one graph per step."""
     dev = "cuda"
-    # LJ13 basin hopping: 1 chain x 8 candidates x 200 steps, FP64, one graph per step
     w = inputs.lj13_bh()
     off, x = w.starts()
     b = lj.ClusterBatch(off, device=dev)
@@ -182,26 +201,32 @@ def workloads(lj, inputs, torch, stream, oracle=None):
         oracle.bh_run(off, xc, st, oracle.bh_params(1, w.cands, kT=w.kT, seed=w.seed),
                       oracle.lbfgs_params(), w.steps)
         entry["cpu_oracle_chain_steps_per_s"] = w.steps / (time.perf_counter() - t0)
-    res[w.name] = entry
-    # uneven batch and large clusters: one minimisation call each
-    for w, params in ((inputs.uneven_batch(), lj.lbfgs_params()),
-                      (inputs.large_clusters(), lj.lbfgs_params(max_iter=500, polish=0))):
-        off, x = w.starts()
-        b = lj.ClusterBatch(off, device=dev)
-        xd = torch.from_numpy(x).to(dev)
-        pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
-        entry = {}
-        for prec in ("mixed", "fp64"):
-            ms, r = timed(torch, stream, lambda: lj.minimize(b, xd, params, prec, stream=stream))
-            st = r["status"].cpu().numpy()
-            ev = r["evals"].cpu().numpy().astype(np.int64)
-            entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
-                           "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
-                           "converged_frac": float(np.mean(st == lj.CONVERGED)),
-                           "median_iters": float(np.median(r["iters"].cpu().numpy()))}
-        entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
-        res[w.name] = entry
-    # the Morse pair (range 6) on the LJ38 batch shape: FP64 and mixed
+    return {w.name: entry}
+
+
+def one_call(lj, w, params, torch, stream):
+    """One minimisation call over the whole batch (uneven sizes, or N = 1000)."""
+    dev = "cuda"
+    off, x = w.starts()
+    b = lj.ClusterBatch(off, device=dev)
+    xd = torch.from_numpy(x).to(dev)
+    pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
+    entry = {}
+    for prec in ("mixed", "fp64"):
+        ms, r = timed(torch, stream, lambda: lj.minimize(b, xd, params, prec, stream=stream))
+        st = r["status"].cpu().numpy()
+        ev = r["evals"].cpu().numpy().astype(np.int64)
+        entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
+                       "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
+                       "converged_frac": float(np.mean(st == lj.CONVERGED)),
+                       "median_iters": float(np.median(r["iters"].cpu().numpy()))}
+    entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
+    return {w.name: entry}
+
+
+def morse_batch(lj, inputs, torch, stream, oracle):
+    """The Morse pair (range 6) on the LJ38 batch shape: FP64 and mixed."""
+    dev = "cuda"
     w = inputs.morse38_batch()
     off, x = w.starts()
     b = lj.ClusterBatch(off, device=dev, pair=w.extra["pair"], rho=w.extra["rho"])
@@ -225,8 +250,12 @@ def workloads(lj, inputs, torch, stream, oracle=None):
         oracle.minimize(off[:sub + 1], x[:, :off[sub]], oracle.lbfgs_params(pair="morse",
                                                                             rho=w.extra["rho"]))
         entry["cpu_oracle_minimisations_per_s"] = sub / (time.perf_counter() - t0)
-    res[w.name] = entry
-    # many chains: 512 chains x 8 candidates, mixed (polish of accepted) and FP64
+    return {w.name: entry}
+
+
+def many_chains(lj, inputs, torch, stream):
+    """512 chains x 8 candidates, mixed (polish of accepted) and FP64."""
+    dev = "cuda"
     w = inputs.many_chains()
     off, x = w.starts()
     b = lj.ClusterBatch(off, device=dev)
@@ -241,8 +270,7 @@ def workloads(lj, inputs, torch, stream, oracle=None):
         entry[prec] = {"ms_per_step": ms / 20, "chain_steps_per_s": b.num * 20 / (ms * 1e-3),
                        "minimisations_per_s": b.num * w.cands * 20 / (ms * 1e-3)}
     entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms_per_step"] / entry["mixed"]["ms_per_step"]
-    res[w.name] = entry
-    return res
+    return {w.name: entry}
 
 
 def mixed_result_errors(lj, O, batch, starts, params, off, hm, stream, torch):
@@ -281,7 +309,7 @@ def main():
     ap.add_argument("--no-pair", action="store_true", help="skip the standalone pair kernel")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other benchmark workloads")
-    ap.add_argument("--only", choices=["mixed", "fp64", "pair"],
+    ap.add_argument("--only", choices=["mixed", "fp64", "pair", *WORKLOADS],
                     help="run one leg only and print its timing (for profiler runs)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run a plain 256 MiB device-to-device copy 5 times (calibrates the "
@@ -311,6 +339,11 @@ def main():
         stream.synchronize()
         print(json.dumps({"copy_ref_bytes_read": nbytes, "copy_ref_bytes_written": nbytes,
                           "launches": 5}), flush=True)
+        return
+    if args.only in WORKLOADS:
+        from paper_2510_25938_amd import inputs as inputs_mod
+        res = workloads(lj, inputs_mod, torch, stream, None, only=args.only)
+        print(json.dumps({"only": args.only, "workload": res}), flush=True)
         return
     wl = lj38_batch(args.count)
     off, x = wl.starts()
