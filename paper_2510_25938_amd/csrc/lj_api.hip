@@ -357,19 +357,18 @@ lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj:
                                    reinterpret_cast<int32_t*>(ws + L.cs), nullptr, d, mixed,
                                    L.cand_min, ws + L.min, st);
     if (r != LJ_OK) return r;
+    // without a polish, decide also finalizes the step (one launch fewer)
     LJ_HIP_TRY(lj::launch_decide(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, xc, ce, dec,
-                                 st));
-    double* pe = nullptr;
-    if (mixed) {
-        pe = reinterpret_cast<double*>(ws + L.pe);
-        lj::LbfgsDev d64 = to_dev(lp);
-        r = enqueue_minimize(ch, dec + ch->num, s.xyz_cur, pe, reinterpret_cast<double*>(ws + L.pg),
-                             reinterpret_cast<int32_t*>(ws + L.pi),
-                             reinterpret_cast<int32_t*>(ws + L.pv),
-                             reinterpret_cast<int32_t*>(ws + L.ps), nullptr, d64, 0, L.polish_min,
-                             ws + L.min, st);
-        if (r != LJ_OK) return r;
-    }
+                                 mixed ? nullptr : &tr, st));
+    if (!mixed) return LJ_OK;
+    // FP64 polish of the accepted candidates (the active mask is the accepted flags)
+    double* pe = reinterpret_cast<double*>(ws + L.pe);
+    r = enqueue_minimize(ch, dec + ch->num, s.xyz_cur, pe, reinterpret_cast<double*>(ws + L.pg),
+                         reinterpret_cast<int32_t*>(ws + L.pi),
+                         reinterpret_cast<int32_t*>(ws + L.pv),
+                         reinterpret_cast<int32_t*>(ws + L.ps), nullptr, to_dev(lp), 0,
+                         L.polish_min, ws + L.min, st);
+    if (r != LJ_OK) return r;
     LJ_HIP_TRY(lj::launch_finalize(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, ce, dec, pe,
                                    tr, st));
     return LJ_OK;

@@ -47,14 +47,47 @@ __global__ __launch_bounds__(64) void perturb_kernel(const int32_t* coff, int ch
     }
 }
 
+// Bookkeeping once the accepted structure is final (after its polish, if
+// any): the current energy becomes the polished one, the best accepted energy
+// is updated, and trace row k is written.  Returns whether the best accepted
+// structure improved.
+__device__ int finalize_chain(int c, BhStateDev s, BhDev p, const double* ecand, int sel, int acc,
+                              const double* polish_e, BhTraceDev tr) {
+    int imp = 0;
+    if (acc) {
+        if (polish_e) s.e_cur[c] = polish_e[c];
+        if (s.e_cur[c] < s.e_best_acc[c]) {
+            s.e_best_acc[c] = s.e_cur[c];
+            imp = 1;
+        }
+    }
+    const int64_t k = s.step_index[c] - 1;
+    if (k >= 0 && k < tr.cap) {
+        const int64_t r = (int64_t)c * tr.cap + k;
+        if (tr.e_trial) tr.e_trial[r] = sel >= 0 ? ecand[(int64_t)c * p.cands + sel] : __builtin_nan("");
+        if (tr.accepted) tr.accepted[r] = (int8_t)acc;
+        if (tr.e_best) tr.e_best[r] = s.e_best_seen[c];
+        if (tr.e_best_acc) tr.e_best_acc[r] = s.e_best_acc[c];
+        if (tr.e_cur) tr.e_cur[r] = s.e_cur[c];
+        if (tr.step) tr.step[r] = s.step[c];
+        if (tr.e_cand)
+            for (int j = 0; j < p.cands; ++j)
+                tr.e_cand[r * p.cands + j] = ecand[(int64_t)c * p.cands + j];
+    }
+    return imp;
+}
+
 // Steps 3-5.  One workgroup per chain; lane 0 takes the decisions, then the
 // whole workgroup copies an accepted candidate into the current structure.
-// dec[c] = selected candidate, dec[chains + c] = accepted flag.
+// dec[c] = selected candidate, dec[chains + c] = accepted flag.  With FIN
+// (no polish follows) the same workgroup also does the final bookkeeping of
+// the step, which otherwise runs in finalize_kernel after the polish.
+template <bool FIN>
 __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int chains, int max_n,
                                                     int64_t total_chain, BhStateDev s, BhDev p,
                                                     const double* xc, const double* ecand,
-                                                    int32_t* dec) {
-    __shared__ int sh_sel, sh_acc;
+                                                    int32_t* dec, BhTraceDev tr) {
+    __shared__ int sh_sel, sh_acc, sh_imp;
     const int c = blockIdx.x;
     if (threadIdx.x == 0) {
         const int64_t k = s.step_index[c];
@@ -98,6 +131,7 @@ __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int cha
         dec[chains + c] = acc;
         sh_sel = sel;
         sh_acc = acc;
+        sh_imp = FIN ? finalize_chain(c, s, p, ecand, sel, acc, nullptr, tr) : 0;
     }
     __syncthreads();
     if (!sh_acc) return;
@@ -107,44 +141,22 @@ __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int cha
     const int64_t total_c = total_chain * p.cands;
     const int64_t co = (int64_t)p.cands * oc + (int64_t)sh_sel * n;
     for (int a = threadIdx.x; a < n; a += blockDim.x)
-        for (int d = 0; d < 3; ++d) s.xyz_cur[d * total_chain + oc + a] = xc[d * total_c + co + a];
+        for (int d = 0; d < 3; ++d) {
+            const double v = xc[d * total_c + co + a];
+            s.xyz_cur[d * total_chain + oc + a] = v;
+            if (FIN && sh_imp) s.xyz_best[d * total_chain + oc + a] = v;
+        }
 }
 
-// Bookkeeping after the optional polish of the accepted structure: the
-// current energy becomes the polished one, the best accepted structure is
-// updated, and trace row k is written.
+// Final bookkeeping of a step whose accepted structure was polished in
+// between (finalize_chain), then the best accepted structure is updated.
 __global__ __launch_bounds__(64) void finalize_kernel(const int32_t* coff, int chains, int max_n,
                                                       int64_t total_chain, BhStateDev s, BhDev p,
                                                       const double* ecand, const int32_t* dec,
                                                       const double* polish_e, BhTraceDev tr) {
     __shared__ int sh_imp;
     const int c = blockIdx.x;
-    if (threadIdx.x == 0) {
-        const int sel = dec[c];
-        const int acc = dec[chains + c];
-        int imp = 0;
-        if (acc) {
-            if (polish_e) s.e_cur[c] = polish_e[c];
-            if (s.e_cur[c] < s.e_best_acc[c]) {
-                s.e_best_acc[c] = s.e_cur[c];
-                imp = 1;
-            }
-        }
-        const int64_t k = s.step_index[c] - 1;
-        if (k >= 0 && k < tr.cap) {
-            const int64_t r = (int64_t)c * tr.cap + k;
-            if (tr.e_trial) tr.e_trial[r] = sel >= 0 ? ecand[(int64_t)c * p.cands + sel] : __builtin_nan("");
-            if (tr.accepted) tr.accepted[r] = (int8_t)acc;
-            if (tr.e_best) tr.e_best[r] = s.e_best_seen[c];
-            if (tr.e_best_acc) tr.e_best_acc[r] = s.e_best_acc[c];
-            if (tr.e_cur) tr.e_cur[r] = s.e_cur[c];
-            if (tr.step) tr.step[r] = s.step[c];
-            if (tr.e_cand)
-                for (int j = 0; j < p.cands; ++j)
-                    tr.e_cand[r * p.cands + j] = ecand[(int64_t)c * p.cands + j];
-        }
-        sh_imp = imp;
-    }
+    if (threadIdx.x == 0) sh_imp = finalize_chain(c, s, p, ecand, dec[c], dec[chains + c], polish_e, tr);
     __syncthreads();
     if (!sh_imp) return;
     const int oc = coff[c];
@@ -164,9 +176,13 @@ hipError_t launch_perturb(const int32_t* coff, int chains, int max_n, int64_t to
 
 hipError_t launch_decide(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                          BhStateDev s, BhDev p, const double* xc, const double* ecand,
-                         int32_t* dec, hipStream_t st) {
-    hipLaunchKernelGGL(decide_kernel, dim3(chains), dim3(64), 0, st, coff, chains, max_n,
-                       total_chain, s, p, xc, ecand, dec);
+                         int32_t* dec, const BhTraceDev* fin, hipStream_t st) {
+    if (fin)
+        hipLaunchKernelGGL(decide_kernel<true>, dim3(chains), dim3(64), 0, st, coff, chains,
+                           max_n, total_chain, s, p, xc, ecand, dec, *fin);
+    else
+        hipLaunchKernelGGL(decide_kernel<false>, dim3(chains), dim3(64), 0, st, coff, chains,
+                           max_n, total_chain, s, p, xc, ecand, dec, BhTraceDev{});
     return hipGetLastError();
 }
 

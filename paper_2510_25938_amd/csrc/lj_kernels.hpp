@@ -107,9 +107,11 @@ struct BhTraceDev {
 
 hipError_t launch_perturb(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                           BhStateDev s, BhDev p, double* xc, int32_t* cand_off, hipStream_t st);
+// fin != nullptr: no polish follows, so the same launch also does the step's
+// final bookkeeping (trace row fin) and finalize is not launched.
 hipError_t launch_decide(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                          BhStateDev s, BhDev p, const double* xc, const double* ecand,
-                         int32_t* dec, hipStream_t st);
+                         int32_t* dec, const BhTraceDev* fin, hipStream_t st);
 hipError_t launch_finalize(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                            BhStateDev s, BhDev p, const double* ecand, const int32_t* dec,
                            const double* polish_e, BhTraceDev tr, hipStream_t st);

@@ -709,8 +709,11 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* offset, int n
     }
     __syncthreads();
     if (t == 0) {
+        // descending exclusive scan of the size counts; sizes above max_n were
+        // rejected, so their counts (and scan values) are zero: start at max_n
+        const int top = max_n < LJ_MAX_ATOMS_MIN ? max_n : LJ_MAX_ATOMS_MIN;
         int run = 0;
-        for (int k = LJ_MAX_ATOMS_MIN; k >= 0; --k) {
+        for (int k = top; k >= 0; --k) {
             const int c = cnt[k];
             cnt[k] = run;
             run += c;
