@@ -115,6 +115,9 @@ typedef struct {
  *   grad    [3][total_atoms] device, written; may be NULL (energy only).
  *   precision LJ_FP64 or LJ_MIXED.
  * N_b = 0 or 1 gives E = 0 and g = 0.  Coincident atoms give a non-finite E.
+ * A cluster above max_n (a broken precondition) is evaluated as usual if it
+ * fits the launch shape chosen for max_n; otherwise its E is NaN and its
+ * gradient is not written.
  * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED (max_n > LJ_MAX_ATOMS_EVAL), LJ_E_HIP.
  */
 lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double* energy,

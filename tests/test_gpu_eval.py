@@ -7,6 +7,8 @@ coordinates is bounded by 128 u32 times the sums of absolute pair terms (a
 standard a-priori bound: about 50 u32 for the pair arithmetic, including the
 1-ulp v_rcp_f32, plus 64 u32 for FP32 accumulation over a 64-partner tile).
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -240,3 +242,27 @@ def test_mixed_tiles_across_tile_counts(sizes):
         a, z = off[k], off[k + 1]
         net = np.abs(g[:, a:z].sum(axis=1))
         assert np.all(net <= 128 * U32 * gabs[:, a:z].sum(axis=1))
+
+
+def test_cluster_above_max_n_that_fits_the_launch_shape_is_evaluated():
+    """The evaluation launch is shaped for the descriptor's max_n: a larger
+    cluster that still fits that shape is evaluated as usual, one that does
+    not gets a NaN energy."""
+    sizes = [100, 30, 0, 0, 0, 0, 0]
+    off, x = random_starts(sizes, 55)
+    b, xd = to_dev(off, x)
+    desc = b.desc(max_n=20)  # total 130 <= 7 * 20 passes the host check
+    w, a = lj.get_schedule(lj.SCHED_EVAL, "fp64", 20)
+    assert 30 <= 64 * w * a < 100  # the shape for 20 atoms holds the 30, not the 100
+    E = torch.full((len(sizes),), 7.0, dtype=torch.float64, device=xd.device)
+    g = torch.zeros_like(xd)
+    announce("eval bad size fp64")
+    rc = lj.lib().lj_energy_grad_batch(C.byref(desc), xd.data_ptr(), E.data_ptr(), g.data_ptr(),
+                                       lj.FP64, None)
+    assert rc == lj.OK
+    torch.cuda.synchronize()
+    Eh, gh = E.cpu().numpy(), g.cpu().numpy()
+    Eo, go = O.energy_grad(off, x)
+    assert np.isnan(Eh[0])
+    assert Eh[1] == Eo[1] and np.array_equal(gh[:, 100:130], go[:, 100:130])
+    assert np.all(Eh[2:] == 0.0)

@@ -242,3 +242,57 @@ def test_autotune_short_workspace_is_rejected():
     st = L.lj_autotune(C.byref(b.desc()), xd.data_ptr(), lj.MIXED, ws.data_ptr(), nb - 1, None,
                        C.byref(t0), C.byref(t1))
     assert st == lj.E_WORKSPACE and t0.value == -2.0 and t1.value == -2.0
+
+
+def test_largest_supported_cluster():
+    """A cluster of LJ_MAX_ATOMS_MIN atoms beside small ones: FP64 bit-identical
+    to the oracle over a capped run; without polish the mixed path reports the
+    oracle's FP64 energy at the coordinates it returns."""
+    off, x = random_starts([lj.MAX_ATOMS_MIN, 1, 13], 51)
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params(max_iter=8)
+    announce(f"minimize fp64 N={lj.MAX_ATOMS_MIN} cap 8")
+    r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    assert_same(r, O.minimize(off, x, oracle_params(p)))
+    announce(f"minimize mixed N={lj.MAX_ATOMS_MIN} cap 8 no polish")
+    rm = host_dict(lj.minimize(b, xd, lj.lbfgs_params(max_iter=8, polish=0), "mixed"))
+    Eo, _ = O.energy_grad(off, rm["xyz"])
+    assert np.array_equal(rm["energy"], Eo)
+
+
+def test_cluster_above_max_n_is_flagged_and_left_alone():
+    """A cluster larger than the descriptor's max_n gets LJ_BADSIZE and keeps
+    its coordinates; the other clusters are minimised as usual."""
+    sizes = [13, 30, 2]
+    off, x = random_starts(sizes, 53)
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params()
+    desc = b.desc(max_n=20)  # 30 > 20; total 45 <= 3 * 20 passes the host check
+    dev = xd.device
+    sub_off = np.array([0, 13, 15], np.int32)
+    sub_x = np.ascontiguousarray(np.concatenate([x[:, 0:13], x[:, 43:45]], axis=1))
+    ro = O.minimize(sub_off, sub_x, oracle_params(p))
+    for prec in (lj.FP64, lj.MIXED):
+        announce(f"minimize bad size prec={prec}")
+        xw = xd.clone()
+        e = torch.full((3,), 7.0, dtype=torch.float64, device=dev)
+        gn = e.clone()
+        it = torch.full((3,), -5, dtype=torch.int32, device=dev)
+        ev, st = it.clone(), it.clone()
+        nb = int(lj.lib().lj_minimize_workspace_bytes(C.byref(desc), C.byref(p), prec))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        rc = lj.lib().lj_bh_minimize_batch(C.byref(desc), xw.data_ptr(), e.data_ptr(),
+                                           gn.data_ptr(), it.data_ptr(), ev.data_ptr(),
+                                           st.data_ptr(), None, C.byref(p), prec, ws.data_ptr(),
+                                           nb, None)
+        assert rc == lj.OK
+        torch.cuda.synchronize()
+        status = st.cpu().numpy()
+        assert list(status) == [lj.CONVERGED, lj.BADSIZE, lj.CONVERGED]
+        assert torch.equal(xw[:, 13:43], xd[:, 13:43])
+        if prec == lj.FP64:
+            xo = xw.cpu().numpy()
+            assert np.array_equal(xo[:, 0:13], ro["xyz"][:, 0:13])
+            assert np.array_equal(xo[:, 43:45], ro["xyz"][:, 13:15])
+            assert np.array_equal(e.cpu().numpy()[[0, 2]], ro["energy"])
