@@ -118,7 +118,6 @@ def test_offsets_above_max_n_are_rejected_per_cluster():
     b, xd = to_dev(off, x)
     E = torch.empty(3, dtype=torch.float64, device="cuda")
     desc = b.desc(max_n=64)  # lies: cluster 1 has 70 atoms
-    import ctypes as C
     st = lj.lib().lj_energy_grad_batch(C.byref(desc), C.c_void_p(xd.data_ptr()),
                                        C.c_void_p(E.data_ptr()), None, lj.FP64,
                                        C.c_void_p(torch.cuda.current_stream().cuda_stream))
