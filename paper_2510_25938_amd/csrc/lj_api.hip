@@ -208,14 +208,20 @@ struct SideStreams {
 };
 std::mutex g_side_mu;
 std::map<std::pair<int, hipStream_t>, SideStreams*> g_side;
+constexpr size_t kMaxSideSets = 16;  // beyond this, classes run in turn on the caller's stream
 
+// out = nullptr (and LJ_OK) once kMaxSideSets caller streams have a set.
 lj_status side_streams(hipStream_t caller, SideStreams*& out) {
+    out = nullptr;
     int dev = 0;
     LJ_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_side_mu);
-    SideStreams*& slot = g_side[{dev, caller}];
-    if (!slot) slot = new SideStreams();  // lives until the process ends
-    SideStreams* ss = slot;
+    auto it = g_side.find({dev, caller});
+    if (it == g_side.end()) {
+        if (g_side.size() >= kMaxSideSets) return LJ_OK;
+        it = g_side.emplace(std::make_pair(dev, caller), new SideStreams()).first;  // kept until exit
+    }
+    SideStreams* ss = it->second;
     if (!ss->ready) {
         for (int c = 0; c < lj::kNumClasses; ++c) {
             LJ_HIP_TRY(hipStreamCreateWithFlags(&ss->s[c], hipStreamNonBlocking));
@@ -262,6 +268,14 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     SideStreams* ss = nullptr;
     lj_status r = side_streams(st, ss);
     if (r != LJ_OK) return r;
+    if (!ss) {  // no side streams for this caller stream: the classes run in turn
+        for (int c = L.top_class; c >= 0; --c) {
+            a.cls = c;
+            a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
+            LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.narrow[c], L.grid[c], a, st));
+        }
+        return LJ_OK;
+    }
     std::lock_guard<std::mutex> lk(ss->mu);
     LJ_HIP_TRY(hipEventRecord(ss->fork, st));
     for (int c = L.top_class; c >= 0; --c) {  // largest clusters first
@@ -375,10 +389,13 @@ lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj:
 }
 
 // HIP-graph cache of one basin-hopping step, keyed by every argument byte.
+// `done` is recorded after each launch, so an evicted graph is destroyed only
+// once its last launch has finished.
 struct GraphEntry {
     std::vector<unsigned char> key;
     int device;
     hipGraphExec_t exec;
+    hipEvent_t done;
 };
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
@@ -541,33 +558,47 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
     key_add(key, ws_bytes);
     key_add(key, st);
     key_add(key, large_schedule(precision));  // a graph keeps the launch shapes it captured
-    hipGraphExec_t exec = nullptr;
+    // Graphs are launched with the cache locked, so another thread's insertion
+    // cannot evict and destroy a graph between its lookup and its launch.
     {
         std::lock_guard<std::mutex> lk(g_graph_mu);
         for (auto& e : g_graphs)
-            if (e.device == dev && e.key == key) exec = e.exec;
+            if (e.device == dev && e.key == key) {
+                for (int k = 0; k < num_steps; ++k) LJ_HIP_TRY(hipGraphLaunch(e.exec, st));
+                LJ_HIP_TRY(hipEventRecord(e.done, st));
+                return LJ_OK;
+            }
     }
-    if (!exec) {
-        LJ_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        s = enqueue_bh_step(chains, sd, pd, params, mixed, td, L, w, st);
-        hipGraph_t graph = nullptr;
-        hipError_t ec = hipStreamEndCapture(st, &graph);
-        if (s != LJ_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return s;
-        }
-        if (ec != hipSuccess) return fail(LJ_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
-        ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ec != hipSuccess) return fail(LJ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ec));
-        std::lock_guard<std::mutex> lk(g_graph_mu);
-        if (g_graphs.size() >= kMaxGraphs) {
-            (void)hipGraphExecDestroy(g_graphs.front().exec);
-            g_graphs.erase(g_graphs.begin());
-        }
-        g_graphs.push_back(GraphEntry{key, dev, exec});
+    LJ_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    s = enqueue_bh_step(chains, sd, pd, params, mixed, td, L, w, st);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (s != LJ_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
     }
+    if (ec != hipSuccess) return fail(LJ_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ec != hipSuccess) return fail(LJ_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ec));
+    hipEvent_t done = nullptr;
+    ec = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (ec != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(LJ_E_HIP, "hipEventCreateWithFlags: %s", hipGetErrorString(ec));
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= kMaxGraphs) {
+        GraphEntry& old = g_graphs.front();
+        (void)hipEventSynchronize(old.done);  // its last launch has finished
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipEventDestroy(old.done);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back(GraphEntry{key, dev, exec, done});
     for (int k = 0; k < num_steps; ++k) LJ_HIP_TRY(hipGraphLaunch(exec, st));
+    LJ_HIP_TRY(hipEventRecord(done, st));
     return LJ_OK;
 }
 

@@ -224,3 +224,26 @@ def test_threads_on_separate_streams_match_serial_runs():
     for o in outs:
         for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
             assert torch.equal(o[k], ref_min[k]), k
+
+
+def test_graph_cache_eviction_and_recapture():
+    """More distinct step graphs than the cache holds: evicted graphs are
+    recaptured on their next use, and every chain equals an eager run."""
+    off, b, r, p = start_chains([13], 61)
+    bh = lj.bh_params(cands=4, seed=5)
+    announce("bh graph cache eviction: 18 chain sets")
+    side = torch.cuda.Stream()
+    graphed = [lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "fp64") for _ in range(18)]
+    eager = [lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "fp64") for _ in range(18)]
+    torch.cuda.synchronize()
+    for rnd in range(2):
+        for g in graphed:  # 18 keys through a 16-entry cache, twice
+            with torch.cuda.stream(side):
+                g.step(2, stream=side)
+    side.synchronize()
+    for e in eager:
+        e.step(4, stream=torch.cuda.default_stream())  # null stream: eager launches
+    torch.cuda.synchronize()
+    for g, e in zip(graphed, eager):
+        for name in ("xyz_cur", "e_cur", "step_size", "win_accepts", "step_index", "xyz_best"):
+            assert torch.equal(getattr(g, name), getattr(e, name)), name

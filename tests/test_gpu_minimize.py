@@ -296,3 +296,22 @@ def test_cluster_above_max_n_is_flagged_and_left_alone():
             assert np.array_equal(xo[:, 0:13], ro["xyz"][:, 0:13])
             assert np.array_equal(xo[:, 43:45], ro["xyz"][:, 13:15])
             assert np.array_equal(e.cpu().numpy()[[0, 2]], ro["energy"])
+
+
+def test_many_caller_streams():
+    """Calls on many caller streams: the first ones get side streams for their
+    size classes, later ones run the classes in turn on the caller's stream.
+    FP64 results are the same on every stream."""
+    off, x = random_starts([13, 80, 150, 38], 57)
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params(max_iter=40)
+    ref = host_dict(lj.minimize(b, xd, p, "fp64"))
+    streams = [torch.cuda.Stream() for _ in range(20)]
+    announce("minimize fp64 on 20 caller streams")
+    outs = []
+    for s in streams:
+        with torch.cuda.stream(s):
+            outs.append(lj.minimize(b, xd, p, "fp64", stream=s))
+    torch.cuda.synchronize()
+    for o in outs:
+        assert_same(host_dict(o), ref)
