@@ -231,8 +231,9 @@ size_t lj_bh_workspace_bytes(const lj_batch* chains, const lj_bh_params* bh,
  * selection are FP64 re-evaluations at the FP32 endpoints) and polishes the
  * accepted candidate in FP64 before it becomes the current structure.
  * One step is captured once into a HIP graph per (shapes, pointers,
- * parameters, stream) and replayed num_steps times; on a stream that is
- * itself being captured the kernels are enqueued directly.
+ * parameters, stream) and replayed num_steps times.  On the legacy NULL
+ * stream, which cannot be captured, and on a stream that is itself being
+ * captured, the kernels are enqueued directly.
  *   chains  batch descriptor of the chains (offset device, sizes host).
  *   state   per-chain state (device arrays), updated in place.
  *   trace   optional (NULL) per-step trace.
