@@ -5,8 +5,8 @@ the library uses for them, on outputs the oracle can compute one by one.
   1024 x LJ38: every cluster (FP64 bitwise; mixed polish from switch points).
   4096 clusters, N uniform on 13..150: every cluster, FP64 bitwise and the
     mixed polish from switch points (the oracle on a pool of host threads).
-  256 x LJ1000, mixed, 500-iteration cap, no polish: FP64 re-evaluation of
-    every result; the FP64 path bitwise on one cluster.
+  256 x LJ1000, 500-iteration cap: mixed (no polish) by FP64 re-evaluation of
+    every result; FP64 bitwise for every cluster and for one cluster alone.
   512 chains, N uniform on 38..75, 8 candidates, mixed + polish of accepted
     minima: decisions of every chain replayed through the oracle.
 """
@@ -113,6 +113,17 @@ def test_lj1000_256_mixed_capped():
     assert np.allclose(gn, r["gnorm"], rtol=1e-12)
     assert set(np.unique(r["status"])) <= {lj.MAXITER, lj.SWITCHED, lj.CONVERGED}
     assert np.all(r["iters"] <= 500) and np.all(r["energy"] < -5000.0)
+
+
+def test_lj1000_256_fp64_every_cluster_bitwise():
+    off, x = large_clusters().starts()
+    p = lj.lbfgs_params(max_iter=500)
+    announce("config lj1000x256 fp64 cap 500")
+    b, xd = to_dev(off, x)
+    r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    ro = oracle_minimize_pool(off, x, oracle_params(p))
+    for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k]), k
 
 
 def test_lj1000_fp64_one_cluster_bitwise():
