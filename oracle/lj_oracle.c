@@ -713,10 +713,12 @@ typedef struct {
  * Full FP64 basin-hopping run of `num_steps` steps for every chain.
  * chain c owns atoms coff[c] .. coff[c+1]-1 of the SoA planes xcur/xbest
  * ([3][total]); its state is st[c]; xcur must hold a local minimum on entry.
+ * Its random streams are those of chain chain0 + c, so a contiguous slice of
+ * a larger set of chains can be run on its own with chain0 = its first index.
  */
 int lj_o_bh_run(int32_t chains, const int32_t* coff, int64_t total, double* xcur, double* xbest,
                 lj_o_chain* st, const lj_o_bh* p, const lj_o_lbfgs* lp, int32_t num_steps,
-                const lj_o_trace* tr) {
+                const lj_o_trace* tr, int32_t chain0) {
     int32_t cap = tr ? tr->cap : 0;
     int maxn = 1;
     for (int c = 0; c < chains; ++c)
@@ -734,7 +736,7 @@ int lj_o_bh_run(int32_t chains, const int32_t* coff, int64_t total, double* xcur
             int64_t k = st[c].step_index;
             for (int j = 0; j < nc; ++j) {
                 double* xc = cand + (size_t)j * 3 * n;
-                lj_o_perturb(n, cur, st[c].step, p->seed, c, k, j, xc);
+                lj_o_perturb(n, cur, st[c].step, p->seed, chain0 + c, k, j, xc);
                 vec3n v;
                 v.c[0] = xc;
                 v.c[1] = xc + n;
@@ -745,7 +747,7 @@ int lj_o_bh_run(int32_t chains, const int32_t* coff, int64_t total, double* xcur
             }
             int32_t acc, imp;
             double esel;
-            int sel = lj_o_bh_decide(&st[c], p, c, ec, &acc, &imp, &esel);
+            int sel = lj_o_bh_decide(&st[c], p, chain0 + c, ec, &acc, &imp, &esel);
             if (acc) memcpy(cur, cand + (size_t)sel * 3 * n, sizeof(double) * 3 * (size_t)n);
             if (imp && xbest)
                 for (int dim = 0; dim < 3; ++dim)

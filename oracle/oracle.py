@@ -63,7 +63,7 @@ def lib():
                                         C.POINTER(i32), C.POINTER(i32), C.POINTER(d)]
         _lib.lj_o_bh_run.argtypes = [i32, vp, i64, vp, vp, C.POINTER(ChainState),
                                      C.POINTER(BHParams), C.POINTER(LBFGSParams), i32,
-                                     C.POINTER(Trace)]
+                                     C.POINTER(Trace), i32]
     return _lib
 
 
@@ -171,10 +171,12 @@ def bh_decide(state, params, chain, ecand):
     return sel, acc.value, imp.value, esel.value
 
 
-def bh_run(coff, xcur, states, params, lparams, num_steps, cap=None, xbest=None):
+def bh_run(coff, xcur, states, params, lparams, num_steps, cap=None, xbest=None, chain0=0):
     """FP64 basin hopping for every chain; updates xcur / xbest / states in place.
 
-    Returns the trace as a dict of [chains][cap] arrays (ecand: [chains][cap][cands]).
+    Chain c draws the random streams of chain chain0 + c (a slice of a larger
+    set of chains run on its own).  Returns the trace as a dict of
+    [chains][cap] arrays (ecand: [chains][cap][cands]).
     """
     coff = _i32(coff)
     chains = coff.size - 1
@@ -191,7 +193,7 @@ def bh_run(coff, xcur, states, params, lparams, num_steps, cap=None, xbest=None)
                                              "e_cur", "step", "ecand")], cap)
     arr = (ChainState * chains)(*states)
     lib().lj_o_bh_run(chains, _p(coff), xcur.shape[-1], _p(xcur), _p(xbest), arr,
-                      C.byref(params), C.byref(lparams), int(num_steps), C.byref(t))
+                      C.byref(params), C.byref(lparams), int(num_steps), C.byref(t), int(chain0))
     for c in range(chains):
         states[c] = arr[c]
     return tr

@@ -121,6 +121,22 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _order(stream, *tensors):
+    """Work on `stream` that uses tensors made on the current stream: the
+    stream first waits for the current stream's queued work, and the tensors
+    are recorded as in use on it (so the caching allocator does not hand their
+    memory out again before that work is done)."""
+    if stream is None or torch.cuda.is_current_stream_capturing():
+        return  # under capture the caller orders its streams
+    cur = torch.cuda.current_stream(stream.device)
+    if stream.cuda_stream == cur.cuda_stream:
+        return
+    stream.wait_stream(cur)
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def precision_code(p):
     if isinstance(p, int):
         return p
@@ -185,6 +201,7 @@ def energy_grad(batch, xyz, precision="fp64", grad=True, stream=None, sigma=1.0,
         return E, g
     E = torch.empty(batch.num, dtype=torch.float64, device=xyz.device)
     g = torch.empty_like(xyz) if grad else None
+    _order(stream, xyz, E, g, batch.offset)
     _check(lib().lj_energy_grad_batch(C.byref(batch.desc()), _ptr(xyz), _ptr(E), _ptr(g),
                                       precision_code(precision), _stream(stream)))
     return E, g
@@ -228,6 +245,7 @@ def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, work
         if nb == 0 and batch.num > 0:
             _check(E_ARG)
         workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    _order(stream, x, workspace, batch.offset, *out.values())
     _check(lib().lj_bh_minimize_batch(C.byref(batch.desc()), _ptr(x), _ptr(out["energy"]),
                                       _ptr(out["gnorm"]), _ptr(out["iters"]), _ptr(out["evals"]),
                                       _ptr(out["status"]), _ptr(out["xyz_switch"]),
@@ -269,6 +287,7 @@ def autotune(batch, xyz, precision="mixed", stream=None, cache=None):
     if nb == 0:
         _check(E_ARG)
     ws = torch.empty(nb, dtype=torch.uint8, device=xyz.device)
+    _order(stream, xyz, ws, batch.offset)
     t_eval, t_min = C.c_float(), C.c_float()
     _check(lib().lj_autotune(C.byref(batch.desc()), _ptr(xyz), prec, _ptr(ws), nb,
                              _stream(stream), C.byref(t_eval), C.byref(t_min)))
@@ -357,8 +376,26 @@ class BasinHopping:
         if nb == 0:
             _check(E_ARG)
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+        # the arrays above are initialised on this stream; a step on another
+        # stream first waits for that (once per stream, see step)
+        self._home = torch.cuda.current_stream(dev)
+        self._ordered = set()
+
+    def _tensors(self):
+        ts = [self.xyz_cur, self.xyz_best, self.e_cur, self.e_best_acc, self.e_best_seen,
+              self.step_size, self.win_accepts, self.step_index, self.workspace, self.batch.offset]
+        if self.trace is not None:
+            ts += [t for t in self.trace.values() if t is not None]
+        return ts
 
     def step(self, num_steps=1, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.xyz_cur.device)
+        if (s.cuda_stream != self._home.cuda_stream and s.cuda_stream not in self._ordered
+                and not torch.cuda.is_current_stream_capturing()):
+            s.wait_stream(self._home)
+            for t in self._tensors():
+                t.record_stream(s)
+            self._ordered.add(s.cuda_stream)
         tr = C.byref(self._trace_desc) if self._trace_desc is not None else None
         _check(lib().lj_bh_step(C.byref(self.batch.desc()), C.byref(self.state), C.byref(self.bh),
                                 C.byref(self.params), self.precision, int(num_steps), tr,

@@ -7,7 +7,8 @@ the library uses for them, on outputs the oracle can compute one by one.
     mixed polish from switch points (the oracle on a pool of host threads).
   256 x LJ1000, 500-iteration cap: mixed (no polish) by FP64 re-evaluation of
     every result; FP64 bitwise for every cluster and for one cluster alone.
-  512 chains, N uniform on 38..75, 8 candidates, mixed + polish of accepted
+  512 chains, N uniform on 38..75, 8 candidates: FP64 bitwise for every chain
+    over 4 steps (trace, candidates and state); mixed + polish of accepted
     minima: decisions of every chain replayed through the oracle.
 """
 import os
@@ -21,7 +22,7 @@ from gpu_util import announce, host, host_dict, to_dev
 from oracle import oracle as O
 from paper_2510_25938_amd import lj
 from paper_2510_25938_amd.inputs import large_clusters, lj38_batch, many_chains, uneven_batch
-from test_gpu_bh import replay_decisions
+from test_gpu_bh import gpu_trace, replay_decisions
 from test_gpu_minimize import oracle_params
 
 pytestmark = pytest.mark.gpu
@@ -158,3 +159,61 @@ def test_chains_512_mixed_replay():
     tr = {k: (None if v is None else v.cpu().numpy()) for k, v in bhx.trace.items()}
     replay_decisions(tr, r["energy"].cpu().numpy(), bh)
     assert np.array_equal(host(bhx.step_index), np.full(b.num, wl.steps))
+
+
+def oracle_bh_pool(off, xmin, e0, bh, lp, steps, step0):
+    """The oracle's FP64 basin hopping for every chain, on up to 16 host
+    threads over contiguous slices of chains (each slice keeps its chains'
+    random streams through chain0)."""
+    off = np.asarray(off, np.int64)
+    nch = off.size - 1
+    nt = max(1, min(16, os.cpu_count() or 1, nch))
+    cuts = np.linspace(0, nch, nt + 1).astype(int)
+    params = O.bh_params(nch, bh.cands, kT=bh.kT, adapt_interval=bh.adapt_interval,
+                         target_rate=bh.target_rate, factor=bh.factor, seed=bh.seed)
+
+    def part(i):
+        a, e = cuts[i], cuts[i + 1]
+        so = (off[a:e + 1] - off[a]).astype(np.int32)
+        xs = np.ascontiguousarray(xmin[:, off[a]:off[e]])
+        xb = xs.copy()
+        st = [O.chain_state(float(q), step0) for q in e0[a:e]]
+        tr = O.bh_run(so, xs, st, params, lp, steps, xbest=xb, chain0=a)
+        return xs, xb, st, tr
+
+    with ThreadPoolExecutor(nt) as ex:
+        parts = list(ex.map(part, range(nt)))
+    xcur = np.concatenate([q[0] for q in parts], axis=1)
+    xbest = np.concatenate([q[1] for q in parts], axis=1)
+    states = [s for q in parts for s in q[2]]
+    tr = {k: np.concatenate([q[3][k] for q in parts]) for k in parts[0][3]}
+    return xcur, xbest, states, tr
+
+
+def test_chains_512_fp64_every_chain_bitwise():
+    wl = many_chains(steps=4)
+    off, x = wl.starts()
+    announce("config 512 chains fp64 (4 steps)")
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params()
+    r = lj.minimize(b, xd, p, "fp64")
+    bh = lj.bh_params(cands=8, kT=0.8, seed=wl.seed)
+    bhx = lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "fp64", step0=wl.step0,
+                          trace_steps=wl.steps, trace_candidates=True)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        bhx.step(wl.steps)
+    side.synchronize()
+    torch.cuda.synchronize()
+    xmin, e0 = r["xyz"].cpu().numpy(), r["energy"].cpu().numpy()
+    xcur, xbest, states, tro = oracle_bh_pool(off, xmin, e0, bh, oracle_params(p), wl.steps,
+                                              wl.step0)
+    tr = gpu_trace(bhx)
+    for k in ("e_trial", "e_best", "e_best_acc", "e_cur", "step"):
+        assert np.array_equal(tr[k], tro[k], equal_nan=True), k
+    assert np.array_equal(tr["accepted"], tro["accepted"])
+    assert np.array_equal(tr["e_cand"], tro["ecand"], equal_nan=True)
+    assert np.array_equal(host(bhx.xyz_cur), xcur)
+    assert np.array_equal(host(bhx.xyz_best), xbest)
+    assert np.array_equal(host(bhx.e_cur), [s.e_cur for s in states])
+    assert np.array_equal(host(bhx.step_size), [s.step for s in states])

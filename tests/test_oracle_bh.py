@@ -163,3 +163,30 @@ def test_lj13_chain_and_resume():
     assert sa[0].e_cur == st[0].e_cur and sa[0].step == st[0].step
     assert np.array_equal(np.concatenate([ta["e_trial"][0][:120], tb["e_trial"][0][120:]]),
                           tr["e_trial"][0], equal_nan=True)
+
+
+def test_chain_slices_reproduce_the_full_run():
+    """bh_run on a contiguous slice of chains with chain0 = its first index
+    gives exactly that slice of the full run (chains are independent and
+    their random streams are keyed by the chain index)."""
+    sizes = [13, 9, 13, 11, 7]
+    off, x = random_starts(sizes, 41)
+    lp = O.lbfgs_params()
+    r = O.minimize(off, x, lp)
+    p = O.bh_params(len(sizes), 3, kT=0.8, seed=41)
+    xf = r["xyz"].copy()
+    sf = [O.chain_state(e, 0.4) for e in r["energy"]]
+    tf = O.bh_run(off, xf, sf, p, lp, 12)
+    a, e = 2, 5
+    so = (np.asarray(off[a:e + 1]) - off[a]).astype(np.int32)
+    xs = np.ascontiguousarray(r["xyz"][:, off[a]:off[e]])
+    ss = [O.chain_state(q, 0.4) for q in r["energy"][a:e]]
+    ts = O.bh_run(so, xs, ss, p, lp, 12, chain0=a)
+    assert np.array_equal(xs, xf[:, off[a]:off[e]])
+    for k in tf:
+        assert np.array_equal(ts[k], tf[k][a:e], equal_nan=True), k
+    assert [q.e_cur for q in ss] == [q.e_cur for q in sf[a:e]]
+    # without the offset the slice draws other streams
+    s0 = [O.chain_state(q, 0.4) for q in r["energy"][a:e]]
+    t0 = O.bh_run(so, np.ascontiguousarray(r["xyz"][:, off[a]:off[e]]), s0, p, lp, 12)
+    assert not np.array_equal(t0["ecand"], tf["ecand"][a:e], equal_nan=True)
