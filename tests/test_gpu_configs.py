@@ -7,6 +7,8 @@ the library uses for them, on outputs the oracle can compute one by one.
     mixed polish from switch points (the oracle on a pool of host threads).
   256 x LJ1000, 500-iteration cap: mixed (no polish) by FP64 re-evaluation of
     every result; FP64 bitwise for every cluster and for one cluster alone.
+  1024 x Morse38 (range 6): every cluster, FP64 bitwise and the mixed polish
+    from switch points.
   512 chains, N uniform on 38..75, 8 candidates: FP64 bitwise for every chain
     over 4 steps (trace, candidates and state); mixed + polish of accepted
     minima: decisions of every chain replayed through the oracle.
@@ -21,9 +23,12 @@ import torch
 from gpu_util import announce, host, host_dict, to_dev
 from oracle import oracle as O
 from paper_2510_25938_amd import lj
-from paper_2510_25938_amd.inputs import large_clusters, lj38_batch, many_chains, uneven_batch
+from paper_2510_25938_amd.inputs import (large_clusters, lj38_batch, many_chains, morse38_batch,
+                                         uneven_batch)
 from test_gpu_bh import gpu_trace, replay_decisions
 from test_gpu_minimize import oracle_params
+from test_gpu_morse import morse_dev
+from test_gpu_morse import oracle_params as morse_params
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +104,25 @@ def test_uneven_4096_mixed_polish_every_cluster():
     ro = oracle_minimize_pool(off, r["xyz_switch"], oracle_params(p))
     for k in ("xyz", "energy", "gnorm", "status"):
         assert np.array_equal(r[k], ro[k]), k
+
+
+def test_morse38_1024_every_cluster():
+    wl = morse38_batch()
+    off, x = wl.starts()
+    rho = wl.extra["rho"]
+    p = lj.lbfgs_params()
+    b, xd = morse_dev(off, x, rho)
+    announce("config morse38x1024 fp64")
+    r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    ro = oracle_minimize_pool(off, x, morse_params(p, rho))
+    for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k]), k
+    announce("config morse38x1024 mixed")
+    rm = host_dict(lj.minimize(b, xd, p, "mixed", switch_point=True))
+    rp = oracle_minimize_pool(off, rm["xyz_switch"], morse_params(p, rho))
+    for k in ("xyz", "energy", "gnorm", "status"):
+        assert np.array_equal(rm[k], rp[k]), k
+    assert np.all(r["status"] == lj.CONVERGED) and np.all(rm["status"] == lj.CONVERGED)
 
 
 def test_lj1000_256_mixed_capped():
