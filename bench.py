@@ -50,6 +50,25 @@ def load_traffic(key):
     return t[key]["hbm_bytes_per_launch"]
 
 
+def load_pair_counters(key, launch_ms):
+    """Counted FLOP/s and VALU issue rate of the pair kernel from committed SQ
+    counter runs (profiles/pair_counters.json), if current, at this run's
+    launch duration."""
+    path = os.path.join(ROOT, "profiles", "pair_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sha") != kernel_source_hash() or key not in t:
+        return None
+    k = t[key]
+    s = launch_ms * 1e-3
+    flop = k["counted_flop_fp32"] + k["counted_flop_fp64"]
+    return {"counted_flop_per_launch": flop, "counted_tflops": flop / s / 1e12,
+            "valu_insts_per_launch": k["valu_insts"],
+            "valu_issue_frac": k["valu_insts"] / s / t["valu_issue_peak_per_s"]}
+
+
 def load_issue(key, launch_ms):
     """VALU issue rate of the minimiser from committed SQ counter runs, if current.
 
@@ -136,6 +155,10 @@ def pair_kernel(lj, large_clusters, dev, stream, torch):
                      "ms": ms, "pair_evals_per_s": pairs / (ms * 1e-3),
                      "achieved_tflops": flops / (ms * 1e-3) / 1e12,
                      "peak_tflops": peak / 1e12, "frac_of_peak": flops / (ms * 1e-3) / peak}
+        cnt = load_pair_counters(f"pair_{prec}_lj1000_256", ms)
+        if cnt is not None:
+            cnt["counted_frac_of_peak"] = cnt["counted_tflops"] * 1e12 / peak
+            out[prec]["counters"] = cnt
     return out
 
 
