@@ -866,6 +866,7 @@ constexpr ClassShape kClassShape[kNumClasses] = {{1, 1, true}, {2, 1, true}, {4,
 constexpr ClassShape kLargeShape[kNumLargeShapes] = {{16, 1, false}, {8, 2, false}, {4, 4, false}};
 
 static ClassShape shape_of(int c, int large, bool narrow) {
+    if (c == 1 && narrow) return {1, 2, true};
     if (c == 2 && narrow) return {3, 1, true};
     return c == 3 ? kLargeShape[large] : kClassShape[c];
 }
@@ -891,6 +892,8 @@ static const void* minimize_kernel_pot(int mixed, int c, int large, bool narrow)
     if (c == 0 && narrow)  // every cluster of the class has at most 16 atoms
         return mixed ? min_kernel_ptr<1, 1, 1, true, POT, 16>()
                      : min_kernel_ptr<0, 1, 1, true, POT, 16>();
+    if (c == 1 && narrow)  // larger classes share the call: one wavefront, two atoms per lane
+        return mixed ? min_kernel_ptr<1, 1, 2, true, POT>() : min_kernel_ptr<0, 1, 2, true, POT>();
     if (c == 2 && narrow)  // every cluster of the class has at most 192 atoms
         return mixed ? min_kernel_ptr<1, 3, 1, true, POT>() : min_kernel_ptr<0, 3, 1, true, POT>();
     if (c < 3) {

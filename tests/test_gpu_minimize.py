@@ -62,6 +62,9 @@ NARROW = {
     "c0_16": (list(range(0, 17)) + [13] * 24, 17),
     # class 2 with at most 192 atoms: three wavefronts (three 64-atom tiles)
     "c2_192": ([129, 150, 192, 13, 100, 160, 129, 185], 193),
+    # class 1 alone: two wavefronts; with a larger cluster in the batch (the
+    # extra one), one wavefront with two atoms per lane
+    "c1_beside": ([65, 100, 128, 80, 13, 127, 96, 70], 129),
 }
 
 
@@ -70,9 +73,11 @@ NARROW = {
 def test_narrow_class_kernels(case, prec):
     """When max_n keeps a size class in the lower part of its range, a leaner
     kernel serves it (16-lane reductions for N <= 16; three wavefronts for
-    129 <= N <= 192).  The same clusters in a batch that also holds one larger
-    cluster run the full kernels: every output is bit-identical between the
-    two, and the FP64 path is bit-identical to the oracle."""
+    129 <= N <= 192), and when larger clusters share the batch the 65-128-atom
+    class runs one wavefront with two atoms per lane.  The same clusters in a
+    batch with one more cluster run the other kernels: every output is
+    bit-identical between the two, and the FP64 path is bit-identical to the
+    oracle."""
     sizes, extra = NARROW[case]
     off, x = random_starts(sizes, 4242)
     p = lj.lbfgs_params()
