@@ -161,12 +161,14 @@ lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int l
     // the plan rejects clusters above max_n, so max_n bounds every class
     L.narrow[0] = max_n <= 16;
     L.narrow[2] = max_n <= 192;
-    // with larger clusters in the batch, the 65-128-atom class runs as one
-    // wavefront with two atoms per lane: about 1.5 times the time per iteration
-    // of two wavefronts, but one SIMD per team instead of two, so twice the
-    // teams drain the class (measured faster in mixed-size batches; with this
-    // class alone its slowest cluster decides and two wavefronts are faster)
-    L.narrow[1] = L.top_class >= 2;
+    // The 65-128-atom class as one wavefront with two atoms per lane: about 1.5
+    // times the time per iteration of two wavefronts, but one SIMD per team
+    // instead of two, so twice the teams drain the class.  That wins when the
+    // class shares the call with larger clusters, and on the FP64 path when
+    // the batch has at least one cluster per SIMD; otherwise the slowest
+    // cluster decides and two wavefronts are faster (mixed-path registers
+    // spill more in the one-wavefront form).
+    L.narrow[1] = L.top_class >= 2 || (!mixed && num >= 4 * di.cus);
     auto grid_for = [&](int c, int large_shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -67,8 +67,9 @@ int class_block(int c, int large, bool narrow);
 size_t class_hist_bytes_per_wg(int c, int large);
 // narrow selects a leaner kernel for class c.  Class 0: every cluster has at
 // most 16 atoms (reductions over one 16-lane row).  Class 2: at most 192 atoms
-// (three wavefronts).  Class 1: larger classes share the call (one wavefront
-// with two atoms per lane, so a team needs one SIMD instead of two).
+// (three wavefronts).  Class 1: larger classes share the call, or an FP64
+// batch has a cluster per SIMD (one wavefront with two atoms per lane, so a
+// team needs one SIMD instead of two).
 const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool narrow);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);

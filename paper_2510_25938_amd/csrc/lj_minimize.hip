@@ -892,7 +892,7 @@ static const void* minimize_kernel_pot(int mixed, int c, int large, bool narrow)
     if (c == 0 && narrow)  // every cluster of the class has at most 16 atoms
         return mixed ? min_kernel_ptr<1, 1, 1, true, POT, 16>()
                      : min_kernel_ptr<0, 1, 1, true, POT, 16>();
-    if (c == 1 && narrow)  // larger classes share the call: one wavefront, two atoms per lane
+    if (c == 1 && narrow)  // one wavefront, two atoms per lane (see min_layout)
         return mixed ? min_kernel_ptr<1, 1, 2, true, POT>() : min_kernel_ptr<0, 1, 2, true, POT>();
     if (c == 2 && narrow)  // every cluster of the class has at most 192 atoms
         return mixed ? min_kernel_ptr<1, 3, 1, true, POT>() : min_kernel_ptr<0, 3, 1, true, POT>();

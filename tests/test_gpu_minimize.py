@@ -320,3 +320,22 @@ def test_many_caller_streams():
     torch.cuda.synchronize()
     for o in outs:
         assert_same(host_dict(o), ref)
+
+
+def test_fp64_class1_kernel_follows_batch_size():
+    """FP64 batches of 65-128-atom clusters with at least one cluster per SIMD
+    run the one-wavefront two-slot kernel, smaller ones two wavefronts: the
+    clusters they share give bit-identical outputs."""
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    sizes = [65 + (k * 37) % 64 for k in range(simds)]
+    off, x = random_starts(sizes, 59)
+    p = lj.lbfgs_params(max_iter=60)
+    announce(f"minimize fp64 class 1: {simds} clusters vs {simds - 1}")
+    b, xd = to_dev(off, x)
+    big = host_dict(lj.minimize(b, xd, p, "fp64"))
+    off2 = off[:simds]  # one cluster fewer
+    b2, xd2 = to_dev(off2, np.ascontiguousarray(x[:, :off2[-1]]))
+    small = host_dict(lj.minimize(b2, xd2, p, "fp64"))
+    for k in KEYS:
+        a = big[k][:, :off2[-1]] if k == "xyz" else big[k][:simds - 1]
+        assert np.array_equal(a, small[k]), k
