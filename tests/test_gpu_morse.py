@@ -102,7 +102,8 @@ def test_mixed_ring_across_sizes(lo, hi, rho):
 
 
 @pytest.mark.parametrize("sizes,rho", [([2, 3, 4, 13, 38, 64], 6.0), ([80, 13, 128], 3.0),
-                                       ([150, 200], 10.0), ([300, 13], 6.0)])
+                                       ([150, 200], 10.0), ([300, 13], 6.0),
+                                       ([80, 150, 13, 127], 6.0)])
 def test_fp64_minimize_bitwise(sizes, rho):
     off, x = random_starts(sizes, 800 + len(sizes))
     p = lj.lbfgs_params()
