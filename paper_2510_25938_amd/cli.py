@@ -20,21 +20,27 @@ import numpy as np
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("molden")
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--cands", type=int, default=8)
-    ap.add_argument("--kT", type=float, default=1.0)
-    ap.add_argument("--step0", type=float, default=0.4)
-    ap.add_argument("--interval", type=int, default=10)
-    ap.add_argument("--target", type=float, default=0.5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--seed", type=int, default=2510)
+    ap.add_argument("molden", help="input .molden file; its first geometry is the start")
+    ap.add_argument("--steps", type=int, default=200, help="basin-hopping steps (default 200)")
+    ap.add_argument("--cands", type=int, default=8,
+                    help="candidates perturbed and minimised per step (default 8)")
+    ap.add_argument("--kT", type=float, default=1.0,
+                    help="Metropolis temperature in units of epsilon (default 1.0)")
+    ap.add_argument("--step0", type=float, default=0.4,
+                    help="initial step size: half the side of the perturbation cube (default 0.4)")
+    ap.add_argument("--interval", type=int, default=10,
+                    help="steps between step-size adaptations (default 10)")
+    ap.add_argument("--target", type=float, default=0.5,
+                    help="target acceptance rate of the adaptation (default 0.5)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="fp64, or FP32 pair arithmetic with FP64 L-BFGS and polish (default fp64)")
+    ap.add_argument("--seed", type=int, default=2510, help="random-stream seed (default 2510)")
     ap.add_argument("--sigma", type=float, default=1.0,
                     help="length unit of the file in LJ sigma (coordinates are divided by it)")
     ap.add_argument("--pair", default="lj", choices=["lj", "morse"],
                     help="pair potential: Eq. (1) or the Morse pair (well depth 1 at r = 1)")
     ap.add_argument("--rho", type=float, default=6.0, help="Morse range")
-    ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--quiet", action="store_true", help="no per-step lines")
     args = ap.parse_args(argv)
 
     import torch
