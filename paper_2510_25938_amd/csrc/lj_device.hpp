@@ -549,8 +549,11 @@ __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ po
 // ordered-pair convention of pairs_mixed (E = 2 sum e_i): a unique pair adds
 // twice its term to the lane that evaluates it.
 // ---------------------------------------------------------------------------
+// One wavefront with two atom slots per lane (the 65-128-atom class beside
+// larger ones) keeps the ordered loop: that kernel is at the register limit,
+// and the tiles' staging registers cost more than their saved arithmetic.
 template <int W, int A>
-constexpr bool kUseTiles = W * A * kWave <= 2048;
+constexpr bool kUseTiles = W * A * kWave <= 2048 && !(W == 1 && A == 2);
 
 // A tile evaluates 32 ring distances per atom within itself, against n
 // partners per atom in the ordered loop: the tiles win above n = 32 (where a
