@@ -579,8 +579,10 @@ static uint64_t stream_word(uint64_t seed, uint64_t chain, uint64_t step, uint64
 
 /* ------------------------------------------------------------------------ */
 /* exp_bh: exp(z) for the Metropolis test.  Cody & Waite (1980) reduction   */
-/* z = k ln2 + r with ln2 split into a high part (low 32 bits zero) and a   */
-/* low part, then the Taylor series of e^r to degree 13 in Horner form      */
+/* z = k ln2 + r with ln2 split into a high part (32 significant bits, 21   */
+/* trailing zero bits: k ln2_hi is exact for |k| < 2^21) and a low part;    */
+/* the split is the published one of fdlibm's e_exp.c (Sun, 1993).  Then    */
+/* the Taylor series of e^r to degree 13 in Horner form                     */
 /* (|r| <= ln2/2, truncation below 2^-53), then scaling by 2^k.  Returns 0  */
 /* for z < -708 or NaN.  The Metropolis test uses z <= 0; the Morse pair     */
 /* uses z <= rho (the reduction and polynomial hold up to z = 709).         */

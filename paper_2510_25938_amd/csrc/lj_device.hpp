@@ -286,7 +286,9 @@ __device__ __forceinline__ double team_max(const double (&vals)[A], TeamScratch<
 
 // ---------------------------------------------------------------------------
 // exp(z) by Cody-Waite reduction z = k ln2 + r (ln2 split into a high part
-// with 32 trailing zero bits and a low part) and the degree-13 Taylor
+// of 32 significant bits, 21 trailing zero bits, so k ln2_hi is exact for
+// |k| < 2^21, and a low part: the published split of fdlibm's e_exp.c,
+// Sun 1993) and the degree-13 Taylor
 // polynomial of e^r in Horner form (|r| <= ln2/2, truncation error below
 // 2^-53), scaled by 2^k; 0 below -708 and for NaN.  Every operation is a
 // correctly rounded IEEE operation, so the result does not depend on the
