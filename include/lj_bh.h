@@ -173,6 +173,34 @@ lj_status lj_bh_minimize_batch(const lj_batch* batch, double* xyz, double* energ
                                double* xyz_switch, const lj_lbfgs_params* params,
                                int32_t precision, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * lj_bh_minimize_batch_noalloc - lj_bh_minimize_batch with no workspace
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * call allocates nothing: its scratch (the work list sorted by N, the
+ * size-class table and the claim counters) is a fixed array of
+ * LJ_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends, and the size classes run one after another on
+ * `stream` (no side streams).  Arguments, outputs and per-cluster results are
+ * those of lj_bh_minimize_batch, bit for bit.
+ * Limits: max_n <= LJ_NOALLOC_MAX_ATOMS (larger clusters keep their L-BFGS
+ * history in workspace memory) and num <= LJ_NOALLOC_MAX_CLUSTERS.
+ * Concurrency: every call on one device shares that device's array; calls
+ * whose work overlaps on one device (other streams, other host threads) race
+ * and give wrong results.  Order them, e.g. on one stream.  The array keeps
+ * the last call's contents; each call rewrites what it reads before using it.
+ * Errors: LJ_E_ARG, LJ_E_UNSUPPORTED (max_n above the limit), LJ_E_WORKSPACE
+ * (more clusters than the array holds), LJ_E_HIP.
+ */
+#define LJ_NOALLOC_SCRATCH_BYTES (1 << 20)
+#define LJ_NOALLOC_MAX_ATOMS 256
+#define LJ_NOALLOC_MAX_CLUSTERS 262016 /* (LJ_NOALLOC_SCRATCH_BYTES - 512) / 4 */
+lj_status lj_bh_minimize_batch_noalloc(const lj_batch* batch, double* xyz, double* energy,
+                                       double* gnorm, int32_t* iters, int32_t* evals,
+                                       int32_t* status, double* xyz_switch,
+                                       const lj_lbfgs_params* params, int32_t precision,
+                                       void* stream);
+
 /* Basin-hopping parameters (host struct). */
 typedef struct {
     int32_t cands;          /* n candidates per chain and step, 1..LJ_MAX_CANDS        */

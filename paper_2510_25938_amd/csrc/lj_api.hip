@@ -246,7 +246,8 @@ lj_status side_streams(hipStream_t caller, SideStreams*& out) {
 lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz, double* energy,
                            double* gnorm, int32_t* iters, int32_t* evals, int32_t* status,
                            double* xyz_switch, const lj::LbfgsDev& p, int mixed,
-                           const MinLayout& L, char* ws, hipStream_t st) {
+                           const MinLayout& L, char* ws, hipStream_t st,
+                           bool concurrent = true) {
     if (b->num == 0) return LJ_OK;
     lj::Plan plan;
     plan.list = reinterpret_cast<int32_t*>(ws + L.list);
@@ -275,9 +276,11 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     }
     // several size classes: run them concurrently on side streams
     SideStreams* ss = nullptr;
-    lj_status r = side_streams(st, ss);
-    if (r != LJ_OK) return r;
-    if (!ss) {  // no side streams for this caller stream: the classes run in turn
+    if (concurrent) {
+        lj_status r = side_streams(st, ss);
+        if (r != LJ_OK) return r;
+    }
+    if (!ss) {  // no side streams (for this caller stream): the classes run in turn
         for (int c = L.top_class; c >= 0; --c) {
             a.cls = c;
             a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
@@ -429,6 +432,34 @@ void key_add(std::vector<unsigned char>& k, const T& v) {
 
 }  // namespace
 
+// Scratch of lj_bh_minimize_batch_noalloc: the work list, size-class table and
+// claim counters of one call, in a fixed array that every device holding the
+// library keeps until the process ends.  Host code never uses this name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[LJ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<char*> g_scratch_ptr;  // per device
+
+lj_status noalloc_scratch(char*& out) {
+    int dev = 0;
+    LJ_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        LJ_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LJ_E_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    out = g_scratch_ptr[dev];
+    return LJ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* lj_status_string(lj_status s) {
@@ -511,6 +542,47 @@ lj_status lj_bh_minimize_batch(const lj_batch* batch, double* xyz, double* energ
     return enqueue_minimize(batch, nullptr, xyz, energy, gnorm, iters, evals, status, xyz_switch,
                             to_dev(params), precision == LJ_MIXED, L, static_cast<char*>(ws),
                             static_cast<hipStream_t>(stream));
+}
+
+lj_status lj_bh_minimize_batch_noalloc(const lj_batch* batch, double* xyz, double* energy,
+                                       double* gnorm, int32_t* iters, int32_t* evals,
+                                       int32_t* status, double* xyz_switch,
+                                       const lj_lbfgs_params* params, int32_t precision,
+                                       void* stream) {
+    g_err.clear();
+    lj_status s = check_batch(batch, LJ_MAX_ATOMS_MIN, "lj_bh_minimize_batch_noalloc");
+    if (s != LJ_OK) return s;
+    if ((s = check_params(params)) != LJ_OK) return s;
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return fail(LJ_E_ARG, "precision = %d is neither LJ_FP64 nor LJ_MIXED", precision);
+    if (batch->num == 0) return LJ_OK;
+    if (!energy || !gnorm || !iters || !evals || !status)
+        return fail(LJ_E_ARG, "an output array is NULL");
+    if (batch->total_atoms > 0 && !xyz) return fail(LJ_E_ARG, "xyz is NULL");
+    if (batch->max_n > LJ_NOALLOC_MAX_ATOMS)
+        return fail(LJ_E_UNSUPPORTED,
+                    "lj_bh_minimize_batch_noalloc: max_n = %d exceeds %d (larger clusters keep "
+                    "their L-BFGS history in a workspace; use lj_bh_minimize_batch)",
+                    batch->max_n, LJ_NOALLOC_MAX_ATOMS);
+    if (batch->num > LJ_NOALLOC_MAX_CLUSTERS)
+        return fail(LJ_E_WORKSPACE,
+                    "lj_bh_minimize_batch_noalloc: %d clusters exceed the %d that its %d-byte "
+                    "static scratch holds; use lj_bh_minimize_batch",
+                    batch->num, LJ_NOALLOC_MAX_CLUSTERS, LJ_NOALLOC_SCRATCH_BYTES);
+    MinLayout L;
+    if ((s = min_layout(batch->num, batch->max_n, precision == LJ_MIXED, batch->pair, L)) != LJ_OK)
+        return s;
+    if (L.total > (size_t)LJ_NOALLOC_SCRATCH_BYTES)
+        return fail(LJ_E_WORKSPACE, "lj_bh_minimize_batch_noalloc: %zu bytes of scratch needed, "
+                    "%d available", L.total, LJ_NOALLOC_SCRATCH_BYTES);
+    char* ws = nullptr;
+    if ((s = noalloc_scratch(ws)) != LJ_OK) return s;
+    // the size classes run in turn on the caller's stream (no side streams are
+    // created); the plan kernel rewrites the whole scratch it uses, counters
+    // included, before the minimiser reads it
+    return enqueue_minimize(batch, nullptr, xyz, energy, gnorm, iters, evals, status, xyz_switch,
+                            to_dev(params), precision == LJ_MIXED, L, ws,
+                            static_cast<hipStream_t>(stream), false);
 }
 
 size_t lj_bh_workspace_bytes(const lj_batch* chains, const lj_bh_params* bh,

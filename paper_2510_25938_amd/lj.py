@@ -22,7 +22,8 @@ SCHED_EVAL, SCHED_MIN_LARGE = 0, 1
 EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
             "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_set_schedule",
             "lj_get_schedule", "lj_autotune_workspace_bytes", "lj_autotune", "lj_status_string",
-            "lj_last_error", "lj_abi_version"]
+            "lj_last_error", "lj_abi_version", "lj_bh_minimize_batch_noalloc"]
+NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_ATOMS, NOALLOC_MAX_CLUSTERS = 1 << 20, 256, 262016
 
 
 PAIRS = {"lj": 0, "morse": 1}  # LJ_PAIR_LJ (Eq. 1), LJ_PAIR_MORSE
@@ -79,6 +80,9 @@ def lib():
         L.lj_bh_minimize_batch.argtypes = [C.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp,
                                            C.POINTER(LbfgsParams), i32, vp, C.c_size_t, vp]
         L.lj_bh_minimize_batch.restype = i32
+        L.lj_bh_minimize_batch_noalloc.argtypes = [C.POINTER(Batch), vp, vp, vp, vp, vp, vp, vp,
+                                                   C.POINTER(LbfgsParams), i32, vp]
+        L.lj_bh_minimize_batch_noalloc.restype = i32
         L.lj_bh_workspace_bytes.argtypes = [C.POINTER(Batch), C.POINTER(BhParams),
                                             C.POINTER(LbfgsParams), i32]
         L.lj_bh_workspace_bytes.restype = C.c_size_t
@@ -251,6 +255,30 @@ def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, work
                                       _ptr(out["status"]), _ptr(out["xyz_switch"]),
                                       C.byref(params), precision_code(precision),
                                       _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def minimize_noalloc(batch, xyz, params=None, precision="fp64", switch_point=False,
+                     stream=None, inplace=False):
+    """`minimize` through the allocation-free entry point: no workspace, the
+    library's fixed per-device scratch instead (at most NOALLOC_MAX_ATOMS atoms
+    per cluster and NOALLOC_MAX_CLUSTERS clusters; overlapping calls on one
+    device race).  The output tensors are allocated here, by the caller."""
+    params = params or lbfgs_params()
+    assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
+    dev = xyz.device
+    x = xyz if inplace else xyz.clone()
+    out = dict(xyz=x, energy=torch.empty(batch.num, dtype=torch.float64, device=dev),
+               gnorm=torch.empty(batch.num, dtype=torch.float64, device=dev),
+               iters=torch.empty(batch.num, dtype=torch.int32, device=dev),
+               evals=torch.empty(batch.num, dtype=torch.int32, device=dev),
+               status=torch.empty(batch.num, dtype=torch.int32, device=dev))
+    out["xyz_switch"] = torch.zeros_like(x) if switch_point else None
+    _order(stream, x, batch.offset, *out.values())
+    _check(lib().lj_bh_minimize_batch_noalloc(
+        C.byref(batch.desc()), _ptr(x), _ptr(out["energy"]), _ptr(out["gnorm"]),
+        _ptr(out["iters"]), _ptr(out["evals"]), _ptr(out["status"]), _ptr(out["xyz_switch"]),
+        C.byref(params), precision_code(precision), _stream(stream)))
     return out
 
 

@@ -86,6 +86,30 @@ def test_argument_errors_are_host_side():
                          None, 0, None) == lj.E_ARG)  # NULL state arrays
 
 
+def test_noalloc_limits_are_host_side():
+    L = lj.lib()
+    p = lj.lbfgs_params()
+    big = lj.Batch(2, 16, lj.NOALLOC_MAX_ATOMS + 1, 2 * lj.NOALLOC_MAX_ATOMS + 2)
+    assert (L.lj_bh_minimize_batch_noalloc(C.byref(big), 16, 16, 16, 16, 16, 16, None,
+                                           C.byref(p), lj.FP64, None) == lj.E_UNSUPPORTED)
+    assert b"use lj_bh_minimize_batch" in L.lj_last_error()
+    many = lj.Batch(lj.NOALLOC_MAX_CLUSTERS + 1, 16, 13, 13 * (lj.NOALLOC_MAX_CLUSTERS + 1))
+    assert (L.lj_bh_minimize_batch_noalloc(C.byref(many), 16, 16, 16, 16, 16, 16, None,
+                                           C.byref(p), lj.MIXED, None) == lj.E_WORKSPACE)
+    assert b"static scratch" in L.lj_last_error()
+    ok = lj.Batch(2, 16, 13, 26)
+    assert (L.lj_bh_minimize_batch_noalloc(C.byref(ok), 16, None, 16, 16, 16, 16, None,
+                                           C.byref(p), lj.FP64, None) == lj.E_ARG)
+    assert (L.lj_bh_minimize_batch_noalloc(C.byref(ok), 16, 16, 16, 16, 16, 16, None,
+                                           C.byref(p), 5, None) == lj.E_ARG)
+    empty = lj.Batch(0, None, 0, 0)
+    assert (L.lj_bh_minimize_batch_noalloc(C.byref(empty), None, None, None, None, None, None,
+                                           None, C.byref(p), lj.FP64, None) == lj.OK)
+    # the published limits: the work list of the largest batch plus the
+    # size-class table and counters (256-byte aligned) fill the scratch exactly
+    assert 4 * lj.NOALLOC_MAX_CLUSTERS + 2 * 256 == lj.NOALLOC_SCRATCH_BYTES
+
+
 def test_empty_batches_are_no_ops():
     L = lj.lib()
     empty = lj.Batch(0, None, 0, 0)
