@@ -238,6 +238,9 @@ typedef struct {
     double* e_cur;      /* e_cur after the step                                      */
     double* step;       /* step size after the step's adaptation                     */
     double* e_cand;     /* every candidate's energy (the values selection used)      */
+    int8_t* polish_status; /* LJ_MIXED: status of the accepted candidate's FP64
+                              polish (LJ_CONVERGED ...); -1 when nothing was
+                              polished (a rejected step, or LJ_FP64)           */
     int32_t capacity_steps;
 } lj_bh_trace;
 
@@ -311,8 +314,13 @@ const char* lj_status_string(lj_status s);
 const char* lj_last_error(void);
 
 /* ABI version of this header (incremented on any incompatible change). */
-#define LJ_ABI_VERSION 2
+#define LJ_ABI_VERSION 3
 int32_t lj_abi_version(void);
+
+/* Number of basin-hopping step graphs captured by this process so far (a
+ * diagnostic of the lj_bh_step graph cache: a call whose arguments match a
+ * cached graph replays it and captures nothing). */
+int64_t lj_bh_graph_captures(void);
 
 #ifdef __cplusplus
 }

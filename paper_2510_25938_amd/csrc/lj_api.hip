@@ -2,6 +2,7 @@
 // scheduling and the HIP-graph cache of the basin-hopping step.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lj_kernels.hpp"
@@ -406,7 +408,7 @@ lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj:
                          L.polish_min, ws + L.min, st);
     if (r != LJ_OK) return r;
     LJ_HIP_TRY(lj::launch_finalize(ch->offset, ch->num, ch->max_n, ch->total_atoms, s, p, ce, dec, pe,
-                                   tr, st));
+                                   reinterpret_cast<const int32_t*>(ws + L.ps), tr, st));
     return LJ_OK;
 }
 
@@ -423,10 +425,68 @@ std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 constexpr size_t kMaxGraphs = 16;
 
+std::atomic<int64_t> g_graph_captures{0};
+
+// Appends the bytes of one scalar or pointer.  Structs are keyed field by
+// field: their padding bytes are indeterminate and would make equal
+// arguments compare unequal.
 template <typename T>
 void key_add(std::vector<unsigned char>& k, const T& v) {
+    static_assert(std::is_arithmetic<T>::value || std::is_pointer<T>::value,
+                  "key structs field by field");
     const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
     k.insert(k.end(), p, p + sizeof(T));
+}
+
+std::vector<unsigned char> step_key(const lj_batch* ch, const lj::BhStateDev& sd,
+                                    const lj::BhDev& pd, const lj_lbfgs_params* lp,
+                                    int32_t precision, const lj::BhTraceDev& td, const void* ws,
+                                    size_t ws_bytes, hipStream_t st) {
+    std::vector<unsigned char> k;
+    k.reserve(320);
+    key_add(k, ch->num);
+    key_add(k, ch->offset);
+    key_add(k, ch->max_n);
+    key_add(k, ch->total_atoms);
+    key_add(k, ch->pair);
+    key_add(k, ch->pair_rho);
+    for (const void* ptr : {(const void*)sd.xyz_cur, (const void*)sd.e_cur, (const void*)sd.step,
+                            (const void*)sd.win_accepts, (const void*)sd.step_index,
+                            (const void*)sd.e_best_seen, (const void*)sd.e_best_acc,
+                            (const void*)sd.xyz_best})
+        key_add(k, ptr);
+    key_add(k, pd.cands);
+    key_add(k, pd.kT);
+    key_add(k, pd.adapt_interval);
+    key_add(k, pd.target_rate);
+    key_add(k, pd.factor);
+    key_add(k, pd.seed);
+    key_add(k, lp->m);
+    key_add(k, lp->gtol);
+    key_add(k, lp->max_iter);
+    key_add(k, lp->max_step);
+    key_add(k, lp->c1);
+    key_add(k, lp->max_ls);
+    key_add(k, lp->curv_eps);
+    key_add(k, lp->gtol_mixed_per_atom);
+    key_add(k, lp->polish);
+    key_add(k, lp->ls_noise);
+    key_add(k, precision);
+    for (const void* ptr : {(const void*)td.e_trial, (const void*)td.accepted,
+                            (const void*)td.e_best, (const void*)td.e_best_acc,
+                            (const void*)td.e_cur, (const void*)td.step, (const void*)td.e_cand,
+                            (const void*)td.polish_status})
+        key_add(k, ptr);
+    key_add(k, td.cap);
+    key_add(k, ws);
+    key_add(k, ws_bytes);
+    key_add(k, st);
+    // a graph keeps the launch shapes it captured: the candidates' schedule
+    // and, on the mixed path, the FP64 schedule of the accepted candidates'
+    // polish
+    key_add(k, large_schedule(precision));
+    key_add(k, large_schedule(LJ_FP64));
+    return k;
 }
 
 
@@ -476,6 +536,8 @@ const char* lj_status_string(lj_status s) {
 const char* lj_last_error(void) { return g_err.c_str(); }
 
 int32_t lj_abi_version(void) { return LJ_ABI_VERSION; }
+
+int64_t lj_bh_graph_captures(void) { return g_graph_captures.load(); }
 
 void lj_lbfgs_defaults(lj_lbfgs_params* p) {
     if (!p) return;
@@ -623,8 +685,9 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
     lj::BhDev pd{bh->cands, bh->kT, bh->adapt_interval, bh->target_rate, bh->factor, bh->seed};
     lj::BhTraceDev td{};
     if (trace)
-        td = lj::BhTraceDev{trace->e_trial, trace->accepted, trace->e_best,         trace->e_best_acc,
-                            trace->e_cur,   trace->step,     trace->e_cand,         trace->capacity_steps};
+        td = lj::BhTraceDev{trace->e_trial, trace->accepted, trace->e_best, trace->e_best_acc,
+                            trace->e_cur,   trace->step,     trace->e_cand, trace->polish_status,
+                            trace->capacity_steps};
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* w = static_cast<char*>(ws);
 
@@ -638,17 +701,8 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
 
     int dev = 0;
     LJ_HIP_TRY(hipGetDevice(&dev));
-    std::vector<unsigned char> key;
-    key_add(key, *chains);
-    key_add(key, sd);
-    key_add(key, pd);
-    key_add(key, *params);
-    key_add(key, precision);
-    key_add(key, td);
-    key_add(key, ws);
-    key_add(key, ws_bytes);
-    key_add(key, st);
-    key_add(key, large_schedule(precision));  // a graph keeps the launch shapes it captured
+    const std::vector<unsigned char> key =
+        step_key(chains, sd, pd, params, precision, td, ws, ws_bytes, st);
     // Graphs are launched with the cache locked, so another thread's insertion
     // cannot evict and destroy a graph between its lookup and its launch.
     {
@@ -688,6 +742,7 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
         g_graphs.erase(g_graphs.begin());
     }
     g_graphs.push_back(GraphEntry{key, dev, exec, done});
+    g_graph_captures.fetch_add(1);
     for (int k = 0; k < num_steps; ++k) LJ_HIP_TRY(hipGraphLaunch(exec, st));
     LJ_HIP_TRY(hipEventRecord(done, st));
     return LJ_OK;

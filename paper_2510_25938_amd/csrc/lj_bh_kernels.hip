@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64) void perturb_kernel(const int32_t* coff, int ch
 // is updated, and trace row k is written.  Returns whether the best accepted
 // structure improved.
 __device__ int finalize_chain(int c, BhStateDev s, BhDev p, const double* ecand, int sel, int acc,
-                              const double* polish_e, BhTraceDev tr) {
+                              const double* polish_e, const int32_t* polish_st, BhTraceDev tr) {
     int imp = 0;
     if (acc) {
         if (polish_e) s.e_cur[c] = polish_e[c];
@@ -70,6 +70,7 @@ __device__ int finalize_chain(int c, BhStateDev s, BhDev p, const double* ecand,
         if (tr.e_best_acc) tr.e_best_acc[r] = s.e_best_acc[c];
         if (tr.e_cur) tr.e_cur[r] = s.e_cur[c];
         if (tr.step) tr.step[r] = s.step[c];
+        if (tr.polish_status) tr.polish_status[r] = (int8_t)(acc && polish_st ? polish_st[c] : -1);
         if (tr.e_cand)
             for (int j = 0; j < p.cands; ++j)
                 tr.e_cand[r * p.cands + j] = ecand[(int64_t)c * p.cands + j];
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int cha
         dec[chains + c] = acc;
         sh_sel = sel;
         sh_acc = acc;
-        sh_imp = FIN ? finalize_chain(c, s, p, ecand, sel, acc, nullptr, tr) : 0;
+        sh_imp = FIN ? finalize_chain(c, s, p, ecand, sel, acc, nullptr, nullptr, tr) : 0;
     }
     __syncthreads();
     if (!sh_acc) return;
@@ -153,10 +154,12 @@ __global__ __launch_bounds__(64) void decide_kernel(const int32_t* coff, int cha
 __global__ __launch_bounds__(64) void finalize_kernel(const int32_t* coff, int chains, int max_n,
                                                       int64_t total_chain, BhStateDev s, BhDev p,
                                                       const double* ecand, const int32_t* dec,
-                                                      const double* polish_e, BhTraceDev tr) {
+                                                      const double* polish_e,
+                                                      const int32_t* polish_st, BhTraceDev tr) {
     __shared__ int sh_imp;
     const int c = blockIdx.x;
-    if (threadIdx.x == 0) sh_imp = finalize_chain(c, s, p, ecand, dec[c], dec[chains + c], polish_e, tr);
+    if (threadIdx.x == 0)
+        sh_imp = finalize_chain(c, s, p, ecand, dec[c], dec[chains + c], polish_e, polish_st, tr);
     __syncthreads();
     if (!sh_imp) return;
     const int oc = coff[c];
@@ -188,9 +191,10 @@ hipError_t launch_decide(const int32_t* coff, int chains, int max_n, int64_t tot
 
 hipError_t launch_finalize(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                            BhStateDev s, BhDev p, const double* ecand, const int32_t* dec,
-                           const double* polish_e, BhTraceDev tr, hipStream_t st) {
+                           const double* polish_e, const int32_t* polish_st, BhTraceDev tr,
+                           hipStream_t st) {
     hipLaunchKernelGGL(finalize_kernel, dim3(chains), dim3(64), 0, st, coff, chains, max_n,
-                       total_chain, s, p, ecand, dec, polish_e, tr);
+                       total_chain, s, p, ecand, dec, polish_e, polish_st, tr);
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ struct BhTraceDev {
     double* e_cur;
     double* step;
     double* e_cand;
+    int8_t* polish_status;
     int32_t cap;
 };
 
@@ -116,6 +117,7 @@ hipError_t launch_decide(const int32_t* coff, int chains, int max_n, int64_t tot
                          int32_t* dec, const BhTraceDev* fin, hipStream_t st);
 hipError_t launch_finalize(const int32_t* coff, int chains, int max_n, int64_t total_chain,
                            BhStateDev s, BhDev p, const double* ecand, const int32_t* dec,
-                           const double* polish_e, BhTraceDev tr, hipStream_t st);
+                           const double* polish_e, const int32_t* polish_st, BhTraceDev tr,
+                           hipStream_t st);
 
 }  // namespace lj

@@ -22,7 +22,8 @@ SCHED_EVAL, SCHED_MIN_LARGE = 0, 1
 EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
             "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_set_schedule",
             "lj_get_schedule", "lj_autotune_workspace_bytes", "lj_autotune", "lj_status_string",
-            "lj_last_error", "lj_abi_version", "lj_bh_minimize_batch_noalloc"]
+            "lj_last_error", "lj_abi_version", "lj_bh_minimize_batch_noalloc",
+            "lj_bh_graph_captures"]
 NOALLOC_SCRATCH_BYTES, NOALLOC_MAX_ATOMS, NOALLOC_MAX_CLUSTERS = 1 << 20, 256, 262016
 
 
@@ -54,7 +55,8 @@ class BhState(C.Structure):
 
 class BhTrace(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("e_trial", "accepted", "e_best", "e_best_acc", "e_cur",
-                                          "step", "e_cand")] + [("capacity_steps", C.c_int32)]
+                                          "step", "e_cand", "polish_status")] + [
+        ("capacity_steps", C.c_int32)]
 
 
 class LJError(RuntimeError):
@@ -105,6 +107,8 @@ def lib():
         L.lj_last_error.restype = C.c_char_p
         L.lj_abi_version.argtypes = []
         L.lj_abi_version.restype = i32
+        L.lj_bh_graph_captures.argtypes = []
+        L.lj_bh_graph_captures.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -396,18 +400,24 @@ class BasinHopping:
                               step=torch.full((C_, trace_steps), float("nan"), **f))
             self.trace["e_cand"] = (torch.full((C_, trace_steps, bh.cands), float("nan"), **f)
                                     if trace_candidates else None)
+            self.trace["polish_status"] = torch.full((C_, trace_steps), -1, dtype=torch.int8,
+                                                     device=dev)
             self._trace_desc = BhTrace(*[None if self.trace[k] is None else self.trace[k].data_ptr()
                                          for k in ("e_trial", "accepted", "e_best", "e_best_acc",
-                                                   "e_cur", "step", "e_cand")], trace_steps)
+                                                   "e_cur", "step", "e_cand", "polish_status")],
+                                       trace_steps)
         nb = int(lib().lj_bh_workspace_bytes(C.byref(batch.desc()), C.byref(bh),
                                              C.byref(self.params), self.precision))
         if nb == 0:
             _check(E_ARG)
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
-        # the arrays above are initialised on this stream; a step on another
-        # stream first waits for that (once per stream, see step)
-        self._home = torch.cuda.current_stream(dev)
-        self._ordered = set()
+        # Every step is ordered after the previous one (or, for the first, after
+        # the initialisation above): a step on a stream other than the last
+        # one's first waits for the event recorded behind the last step.
+        self._last_stream = torch.cuda.current_stream(dev)
+        self._last_event = torch.cuda.Event()
+        self._last_event.record(self._last_stream)
+        self._recorded = {self._last_stream.cuda_stream}
 
     def _tensors(self):
         ts = [self.xyz_cur, self.xyz_best, self.e_cur, self.e_best_acc, self.e_best_seen,
@@ -418,13 +428,24 @@ class BasinHopping:
 
     def step(self, num_steps=1, stream=None):
         s = stream if stream is not None else torch.cuda.current_stream(self.xyz_cur.device)
-        if (s.cuda_stream != self._home.cuda_stream and s.cuda_stream not in self._ordered
-                and not torch.cuda.is_current_stream_capturing()):
-            s.wait_stream(self._home)
-            for t in self._tensors():
-                t.record_stream(s)
-            self._ordered.add(s.cuda_stream)
+        capturing = torch.cuda.is_current_stream_capturing()
+        if not capturing:  # under capture the caller orders its streams
+            if s.cuda_stream != self._last_stream.cuda_stream:
+                s.wait_event(self._last_event)
+            if s.cuda_stream not in self._recorded:
+                for t in self._tensors():
+                    t.record_stream(s)
+                self._recorded.add(s.cuda_stream)
         tr = C.byref(self._trace_desc) if self._trace_desc is not None else None
         _check(lib().lj_bh_step(C.byref(self.batch.desc()), C.byref(self.state), C.byref(self.bh),
                                 C.byref(self.params), self.precision, int(num_steps), tr,
-                                _ptr(self.workspace), self.workspace.numel(), _stream(stream)))
+                                _ptr(self.workspace), self.workspace.numel(), _stream(s)))
+        if not capturing:
+            self._last_event = torch.cuda.Event()
+            self._last_event.record(s)
+            self._last_stream = s
+
+
+def graph_captures():
+    """Step graphs captured by this process so far (lj_bh_step's cache)."""
+    return int(lib().lj_bh_graph_captures())

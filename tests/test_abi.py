@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     L = lj.lib()
-    assert L.lj_abi_version() == 2
+    assert L.lj_abi_version() == 3
     assert L.lj_status_string(lj.OK) == b"LJ_OK"
     for s in (lj.E_ARG, lj.E_HIP, lj.E_WORKSPACE, lj.E_UNSUPPORTED):
         assert L.lj_status_string(s).startswith(b"LJ_E_")

@@ -10,7 +10,7 @@ the library uses for them, on outputs the oracle can compute one by one.
   1024 x Morse38 (range 6): every cluster, FP64 bitwise and the mixed polish
     from switch points.
   512 chains, N uniform on 38..75, 8 candidates: FP64 bitwise for every chain
-    over 4 steps (trace, candidates and state); mixed + polish of accepted
+    over 20 steps, two adaptation windows (trace, candidates and state); mixed + polish of accepted
     minima: decisions of every chain replayed through the oracle.
 """
 import os
@@ -183,6 +183,15 @@ def test_chains_512_mixed_replay():
     tr = {k: (None if v is None else v.cpu().numpy()) for k, v in bhx.trace.items()}
     replay_decisions(tr, r["energy"].cpu().numpy(), bh)
     assert np.array_equal(host(bhx.step_index), np.full(b.num, wl.steps))
+    # every accepted candidate's FP64 polish converged; the current structures
+    # are minima to ||g|| < 1e-6 by the oracle's gradient, with the reported E
+    acc = tr["accepted"] == 1
+    assert np.all(tr["polish_status"][acc] == lj.CONVERGED)
+    assert np.all(tr["polish_status"][~acc] == -1)
+    Eo, go = O.energy_grad(off, host(bhx.xyz_cur))
+    assert np.array_equal(Eo, host(bhx.e_cur))
+    gn = np.sqrt(np.add.reduceat((go * go).sum(axis=0), off[:-1]))
+    assert np.all(gn < 1e-6)
 
 
 def oracle_bh_pool(off, xmin, e0, bh, lp, steps, step0):
@@ -215,9 +224,10 @@ def oracle_bh_pool(off, xmin, e0, bh, lp, steps, step0):
 
 
 def test_chains_512_fp64_every_chain_bitwise():
-    wl = many_chains(steps=4)
+    # 20 steps: two step-size adaptation windows of 10 steps
+    wl = many_chains(steps=20)
     off, x = wl.starts()
-    announce("config 512 chains fp64 (4 steps)")
+    announce("config 512 chains fp64 (20 steps)")
     b, xd = to_dev(off, x)
     p = lj.lbfgs_params()
     r = lj.minimize(b, xd, p, "fp64")
@@ -241,3 +251,7 @@ def test_chains_512_fp64_every_chain_bitwise():
     assert np.array_equal(host(bhx.xyz_best), xbest)
     assert np.array_equal(host(bhx.e_cur), [s.e_cur for s in states])
     assert np.array_equal(host(bhx.step_size), [s.step for s in states])
+    assert np.array_equal(host(bhx.win_accepts), [s.win_accepts for s in states])
+    assert np.array_equal(host(bhx.step_index), np.full(b.num, wl.steps))
+    # the adaptation windows changed step sizes away from s0 on some chains
+    assert np.any(tr["step"][:, -1] != wl.step0)
