@@ -162,19 +162,101 @@ def pair_kernel(lj, large_clusters, dev, stream, torch):
     return out
 
 
-def timed(torch, stream, fn, reps=1):
-    """Average GPU time (ms) of fn() on `stream` over reps calls, after one warm-up."""
+def timed(torch, stream, fn, reps=5, setup=None):
+    """Median GPU time (ms) of fn(arg) on `stream` over `reps` calls, after one
+    warm-up call; arg = setup() is prepared before each call, outside the
+    timed region (None without setup).  Returns (median ms, last result)."""
+    times, out = [], None
     with torch.cuda.stream(stream):
-        out = fn()
-        stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            out = fn()
-        e1.record(stream)
-        stream.synchronize()
-    return e0.elapsed_time(e1) / reps, out
+        for k in range(reps + 1):
+            arg = setup() if setup else None
+            stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn(arg)
+            e1.record(stream)
+            stream.synchronize()
+            if k > 0:
+                times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), out
+
+
+def pool_size():
+    return max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                      else (os.cpu_count() or 1)))
+
+
+def oracle_minimize_pool(O, off, x, params=None, P=None):
+    """The oracle over a batch on P worker threads (contiguous slices of
+    clusters; its C entry point runs without the GIL).  Returns (merged
+    results, wall seconds, P)."""
+    import concurrent.futures as cf
+    off = np.asarray(off, np.int64)
+    B = off.size - 1
+    P = P or pool_size()
+    P = max(1, min(P, B))
+    cuts = np.linspace(0, B, P + 1).astype(int)
+
+    def work(k):
+        a, b = cuts[k], cuts[k + 1]
+        return O.minimize((off[a:b + 1] - off[a]).astype(np.int32),
+                          np.ascontiguousarray(x[:, off[a]:off[b]]), params)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(P) as ex:
+        parts = list(ex.map(work, range(P)))
+    sec = time.perf_counter() - t0
+    merged = {k: np.concatenate([q[k] for q in parts], axis=-1) for k in parts[0]}
+    return merged, sec, P
+
+
+def oracle_chains_pool(O, off, xmin, e0, w, steps, P=None):
+    """The oracle's FP64 basin hopping of a set of chains, one contiguous
+    slice of chains per worker thread (each slice keeps its chains' random
+    streams).  Returns (trace, final states, xcur, wall seconds, P)."""
+    import concurrent.futures as cf
+    off = np.asarray(off, np.int64)
+    nch = off.size - 1
+    P = max(1, min(P or pool_size(), nch))
+    cuts = np.linspace(0, nch, P + 1).astype(int)
+    params = O.bh_params(nch, w.cands, kT=w.kT, seed=w.seed)
+
+    def part(i):
+        a, e = cuts[i], cuts[i + 1]
+        so = (off[a:e + 1] - off[a]).astype(np.int32)
+        xs = np.ascontiguousarray(xmin[:, off[a]:off[e]])
+        st = [O.chain_state(float(q), w.step0) for q in e0[a:e]]
+        tr = O.bh_run(so, xs, st, params, O.lbfgs_params(), steps, chain0=a)
+        return xs, st, tr
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(P) as ex:
+        parts = list(ex.map(part, range(P)))
+    sec = time.perf_counter() - t0
+    tr = {k: np.concatenate([q[2][k] for q in parts]) for k in parts[0][2]}
+    states = [s for q in parts for s in q[1]]
+    xcur = np.concatenate([q[0] for q in parts], axis=1)
+    return tr, states, xcur, sec, P
+
+
+def per_cluster_equal(a, b, off):
+    """Share of clusters whose coordinates, energy and status are identical."""
+    B = off.size - 1
+    return float(np.mean([np.array_equal(a["xyz"][:, off[k]:off[k + 1]],
+                                          b["xyz"][:, off[k]:off[k + 1]])
+                          and a["energy"][k] == b["energy"][k]
+                          and a["status"][k] == b["status"][k] for k in range(B)]))
+
+
+def errors_at_results(O, off, h, pair="lj", rho=6.0):
+    """The oracle's energy and gradient norm at every GPU result: the largest
+    |E_reported - E_oracle| and the largest oracle ||g||."""
+    Eo, go = O.energy_grad(off, h["xyz"], pair=pair, rho=rho)
+    gn = np.sqrt(np.add.reduceat((go * go).sum(axis=0), off[:-1])) if off[-1] > 0 else go
+    return {"energy_abs_err_max_vs_oracle_at_result": float(np.max(np.abs(h["energy"] - Eo))),
+            "gnorm_oracle_at_result_max": float(np.max(gn)),
+            "gnorm_oracle_at_result_median": float(np.median(gn))}
 
 
 WORKLOADS = ("lj13bh", "uneven", "large", "morse", "chains")
@@ -186,20 +268,20 @@ def workloads(lj, inputs, torch, stream, oracle=None, only=None):
     res = {}
     if only in (None, "lj13bh"):
         res.update(lj13_chain(lj, inputs, torch, stream, oracle))
-    for key, w, params in (("uneven", inputs.uneven_batch(), lj.lbfgs_params()),
-                           ("large", inputs.large_clusters(),
-                            lj.lbfgs_params(max_iter=500, polish=0))):
-        if only in (None, key):
-            res.update(one_call(lj, w, params, torch, stream))
+    if only in (None, "uneven"):
+        res.update(uneven_batch(lj, inputs, torch, stream, oracle))
+    if only in (None, "large"):
+        res.update(large_batch(lj, inputs, torch, stream, oracle))
     if only in (None, "morse"):
         res.update(morse_batch(lj, inputs, torch, stream, oracle))
     if only in (None, "chains"):
-        res.update(many_chains(lj, inputs, torch, stream))
+        res.update(many_chains(lj, inputs, torch, stream, oracle))
     return res
 
 
 def lj13_chain(lj, inputs, torch, stream, oracle):
-    """LJ13 basin hopping: 1 chain x 8 candidates x 200 steps, FP64, one graph per step."""
+    """LJ13 basin hopping: 1 chain x 8 candidates x 200 steps, FP64, one graph
+    per step.  The chain object is built outside the timed region."""
     dev = "cuda"
     w = inputs.lj13_bh()
     off, x = w.starts()
@@ -207,93 +289,243 @@ def lj13_chain(lj, inputs, torch, stream, oracle):
     r0 = lj.minimize(b, torch.from_numpy(x).to(dev), lj.lbfgs_params(), "fp64", stream=stream)
     stream.synchronize()
 
-    def chain():
-        c = lj.BasinHopping(b, r0["xyz"], r0["energy"],
-                            lj.bh_params(cands=w.cands, kT=w.kT, seed=w.seed), lj.lbfgs_params(),
-                            "fp64", step0=w.step0)
+    def setup():
+        return lj.BasinHopping(b, r0["xyz"], r0["energy"],
+                               lj.bh_params(cands=w.cands, kT=w.kT, seed=w.seed),
+                               lj.lbfgs_params(), "fp64", step0=w.step0, trace_steps=w.steps)
+
+    def chain(c):
         c.step(w.steps, stream=stream)
         return c
-    ms, c = timed(torch, stream, chain)
+    ms, c = timed(torch, stream, chain, setup=setup)
     e_best = float(c.e_best_acc[0].item())
-    entry = {"chain_steps_per_s": w.steps / (ms * 1e-3), "ms": ms, "best_energy": e_best,
-             "reached_lj13_minimum": abs(e_best + 44.326801) < 1e-6}
+    entry = {"chain_steps_per_s": w.steps / (ms * 1e-3), "ms": ms, "reps": 5, "stat": "median",
+             "best_energy": e_best, "reached_lj13_minimum": abs(e_best + 44.326801) < 1e-6}
     if oracle is not None:
         xc = r0["xyz"].cpu().numpy().copy()
         st = [oracle.chain_state(float(r0["energy"][0].item()), w.step0)]
         t0 = time.perf_counter()
-        oracle.bh_run(off, xc, st, oracle.bh_params(1, w.cands, kT=w.kT, seed=w.seed),
-                      oracle.lbfgs_params(), w.steps)
+        tro = oracle.bh_run(off, xc, st, oracle.bh_params(1, w.cands, kT=w.kT, seed=w.seed),
+                            oracle.lbfgs_params(), w.steps)
         entry["cpu_oracle_chain_steps_per_s"] = w.steps / (time.perf_counter() - t0)
+        entry["cpu_oracle_cores"] = 1
+        tr = {k: v.cpu().numpy() for k, v in c.trace.items() if v is not None}
+        entry["fp64_trace_bitwise"] = bool(
+            all(np.array_equal(tr[k], tro[k], equal_nan=True)
+                for k in ("e_trial", "e_best", "e_best_acc", "e_cur", "step"))
+            and np.array_equal(tr["accepted"], tro["accepted"])
+            and np.array_equal(c.xyz_cur.cpu().numpy(), xc))
     return {w.name: entry}
 
 
-def one_call(lj, w, params, torch, stream):
-    """One minimisation call over the whole batch (uneven sizes, or N = 1000)."""
+def minimize_legs(lj, b, xd, params, torch, stream, pairs):
+    entry, host = {}, {}
+    for prec in ("mixed", "fp64"):
+        ms, r = timed(torch, stream, lambda _: lj.minimize(b, xd, params, prec, stream=stream))
+        h = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+        ev = h["evals"].astype(np.int64)
+        entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
+                       "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
+                       "converged_frac": float(np.mean(h["status"] == lj.CONVERGED)),
+                       "median_iters": float(np.median(h["iters"])),
+                       "max_iters": int(h["iters"].max())}
+        host[prec] = h
+    entry["reps"], entry["stat"] = 5, "median"
+    entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
+    return entry, host
+
+
+def uneven_batch(lj, inputs, torch, stream, O):
+    """4096 clusters, N uniform on 13..150: one call, mixed + polish and FP64;
+    the oracle on the full batch (a pool of threads) and one thread on the
+    first 256 clusters; per-result errors of both paths."""
     dev = "cuda"
+    w = inputs.uneven_batch()
     off, x = w.starts()
     b = lj.ClusterBatch(off, device=dev)
     xd = torch.from_numpy(x).to(dev)
+    params = lj.lbfgs_params()
     pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
-    entry = {}
-    for prec in ("mixed", "fp64"):
-        ms, r = timed(torch, stream, lambda: lj.minimize(b, xd, params, prec, stream=stream))
-        st = r["status"].cpu().numpy()
-        ev = r["evals"].cpu().numpy().astype(np.int64)
-        entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
-                       "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
-                       "converged_frac": float(np.mean(st == lj.CONVERGED)),
-                       "median_iters": float(np.median(r["iters"].cpu().numpy()))}
-    entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
+    entry, host = minimize_legs(lj, b, xd, params, torch, stream, pairs)
+    if O is None:
+        return {w.name: entry}
+    ro, sec, P = oracle_minimize_pool(O, off, x)
+    sub = 256
+    t0 = time.perf_counter()
+    O.minimize(off[:sub + 1], x[:, :off[sub]])
+    sec1 = time.perf_counter() - t0
+    entry["cpu_oracle"] = {
+        "pool": {"minimisations_per_s": b.num / sec, "cores": P,
+                 "sample": f"all {b.num} clusters, {P} worker threads ({sec:.2f} s)"},
+        "one_thread": {"minimisations_per_s": sub / sec1, "cores": 1,
+                       "sample": f"the first {sub} clusters ({sec1:.2f} s)"}}
+    with torch.cuda.stream(stream):
+        rs = lj.minimize(b, xd, params, "mixed", switch_point=True, stream=stream)
+    stream.synchronize()
+    hs = {k: v.cpu().numpy() for k, v in rs.items() if v is not None}
+    rp, _, _ = oracle_minimize_pool(O, off, hs["xyz_switch"])
+    rel = np.abs(host["mixed"]["energy"] - ro["energy"]) / np.abs(ro["energy"])
+    entry["parity"] = {
+        "fp64_bitwise_frac": per_cluster_equal(host["fp64"], ro, off),
+        "mixed_rerun_equals_timed": bool(np.array_equal(hs["xyz"], host["mixed"]["xyz"])),
+        "mixed_polish_bitwise_frac": per_cluster_equal(hs, rp, off),
+        "mixed_same_minimum_frac_1e-6": float(np.mean(rel <= 1e-6)),
+        "mixed_energy_rel_err_median": float(np.median(rel)),
+        **{"mixed_" + k: v for k, v in errors_at_results(O, off, host["mixed"]).items()}}
     return {w.name: entry}
 
 
-def morse_batch(lj, inputs, torch, stream, oracle):
+def large_batch(lj, inputs, torch, stream, O):
+    """256 clusters of N = 1000, 500-iteration cap, mixed without polish and
+    FP64; the oracle on a 32-cluster subset (a pool of threads)."""
+    dev = "cuda"
+    w = inputs.large_clusters()
+    off, x = w.starts()
+    b = lj.ClusterBatch(off, device=dev)
+    xd = torch.from_numpy(x).to(dev)
+    params = lj.lbfgs_params(max_iter=500, polish=0)
+    pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
+    entry, host = minimize_legs(lj, b, xd, params, torch, stream, pairs)
+    if O is None:
+        return {w.name: entry}
+    sub = 32
+    so = off[:sub + 1]
+    ro, sec, P = oracle_minimize_pool(O, so, x[:, :off[sub]], O.lbfgs_params(max_iter=500))
+    entry["cpu_oracle"] = {"minimisations_per_s": sub / sec, "cores": P,
+                           "sample": f"the first {sub} clusters, FP64, {P} worker threads "
+                                     f"({sec:.2f} s)"}
+    h64 = {k: (v[:, :off[sub]] if k == "xyz" else v[:sub]) for k, v in host["fp64"].items()}
+    entry["parity"] = {
+        "fp64_bitwise_frac_subset": per_cluster_equal(h64, ro, so),
+        "fp64_subset": sub,
+        **{"mixed_" + k: v for k, v in errors_at_results(O, off, host["mixed"]).items()}}
+    return {w.name: entry}
+
+
+def morse_batch(lj, inputs, torch, stream, O):
     """The Morse pair (range 6) on the LJ38 batch shape: FP64 and mixed."""
     dev = "cuda"
     w = inputs.morse38_batch()
     off, x = w.starts()
-    b = lj.ClusterBatch(off, device=dev, pair=w.extra["pair"], rho=w.extra["rho"])
+    rho = w.extra["rho"]
+    b = lj.ClusterBatch(off, device=dev, pair=w.extra["pair"], rho=rho)
     xd = torch.from_numpy(x).to(dev)
     pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
-    entry = {"pair": "morse", "rho": w.extra["rho"]}
-    for prec in ("mixed", "fp64"):
-        ms, r = timed(torch, stream, lambda: lj.minimize(b, xd, lj.lbfgs_params(), prec,
-                                                         stream=stream))
-        st = r["status"].cpu().numpy()
-        ev = r["evals"].cpu().numpy().astype(np.int64)
-        entry[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3),
-                       "pair_evals_per_s": float((ev * pairs).sum()) / (ms * 1e-3),
-                       "converged_frac": float(np.mean(st == lj.CONVERGED)),
-                       "median_iters": float(np.median(r["iters"].cpu().numpy())),
-                       "lowest_energy": float(r["energy"].min().item())}
-    entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms"] / entry["mixed"]["ms"]
-    if oracle is not None:
-        sub = 64  # the oracle on the first 64 clusters of the batch
-        t0 = time.perf_counter()
-        oracle.minimize(off[:sub + 1], x[:, :off[sub]], oracle.lbfgs_params(pair="morse",
-                                                                            rho=w.extra["rho"]))
-        entry["cpu_oracle_minimisations_per_s"] = sub / (time.perf_counter() - t0)
+    entry, host = minimize_legs(lj, b, xd, lj.lbfgs_params(), torch, stream, pairs)
+    entry.update(pair="morse", rho=rho)
+    if O is None:
+        return {w.name: entry}
+    op = O.lbfgs_params(pair="morse", rho=rho)
+    sub = 64
+    t0 = time.perf_counter()
+    O.minimize(off[:sub + 1], x[:, :off[sub]], op)
+    sec1 = time.perf_counter() - t0
+    ro, sec, P = oracle_minimize_pool(O, off, x, op)
+    entry["cpu_oracle"] = {
+        "pool": {"minimisations_per_s": b.num / sec, "cores": P,
+                 "sample": f"all {b.num} clusters, {P} worker threads ({sec:.2f} s)"},
+        "one_thread": {"minimisations_per_s": sub / sec1, "cores": 1,
+                       "sample": f"the first {sub} clusters ({sec1:.2f} s)"}}
+    entry["parity"] = {
+        "fp64_bitwise_frac": per_cluster_equal(host["fp64"], ro, off),
+        **{"mixed_" + k: v for k, v in errors_at_results(O, off, host["mixed"], "morse",
+                                                         rho).items()}}
     return {w.name: entry}
 
 
-def many_chains(lj, inputs, torch, stream):
-    """512 chains x 8 candidates, mixed (polish of accepted) and FP64."""
+def many_chains(lj, inputs, torch, stream, O):
+    """512 chains x 8 candidates, mixed (polish of accepted) and FP64: 20 steps
+    per timed run (fresh chains each run, built outside the timed region);
+    the oracle on the first 16 chains for the same 20 steps (a pool of
+    threads; chains are independent, so its rate scales x32 to all 512)."""
     dev = "cuda"
     w = inputs.many_chains()
     off, x = w.starts()
     b = lj.ClusterBatch(off, device=dev)
     r0 = lj.minimize(b, torch.from_numpy(x).to(dev), lj.lbfgs_params(), "fp64", stream=stream)
     stream.synchronize()
-    entry = {"steps_timed": 20, "steps_in_workload": w.steps}
+    steps = 20
+    entry = {"steps_timed": steps, "steps_in_workload": w.steps, "reps": 5, "stat": "median"}
+    chains = {}
     for prec in ("mixed", "fp64"):
-        c = lj.BasinHopping(b, r0["xyz"], r0["energy"], lj.bh_params(cands=w.cands, kT=w.kT,
-                                                                     seed=w.seed),
-                            lj.lbfgs_params(), prec, step0=w.step0)
-        ms, _ = timed(torch, stream, lambda: c.step(20, stream=stream))
-        entry[prec] = {"ms_per_step": ms / 20, "chain_steps_per_s": b.num * 20 / (ms * 1e-3),
-                       "minimisations_per_s": b.num * w.cands * 20 / (ms * 1e-3)}
+        def setup():
+            c = lj.BasinHopping(b, r0["xyz"], r0["energy"],
+                                lj.bh_params(cands=w.cands, kT=w.kT, seed=w.seed),
+                                lj.lbfgs_params(), prec, step0=w.step0, trace_steps=steps,
+                                trace_candidates=True)
+            chains[prec] = c
+            return c
+        ms, _ = timed(torch, stream, lambda c: c.step(steps, stream=stream), setup=setup)
+        entry[prec] = {"ms_per_step": ms / steps, "chain_steps_per_s": b.num * steps / (ms * 1e-3),
+                       "minimisations_per_s": b.num * w.cands * steps / (ms * 1e-3)}
     entry["speedup_mixed_vs_fp64"] = entry["fp64"]["ms_per_step"] / entry["mixed"]["ms_per_step"]
+    if O is None:
+        return {w.name: entry}
+    sub = 16
+    xmin, e0 = r0["xyz"].cpu().numpy(), r0["energy"].cpu().numpy()
+    tro, states, xcur, sec, P = oracle_chains_pool(O, off[:sub + 1], xmin[:, :off[sub]],
+                                                   e0[:sub], w, steps)
+    entry["cpu_oracle"] = {"chain_steps_per_s": sub * steps / sec, "cores": P,
+                           "sample": f"the first {sub} chains x {steps} steps, FP64, {P} worker "
+                                     f"threads ({sec:.2f} s); the same rate holds for 512 chains "
+                                     f"(x32 the time)"}
+    t64 = {k: v.cpu().numpy()[:sub] for k, v in chains["fp64"].trace.items() if v is not None}
+    tm = {k: v.cpu().numpy() for k, v in chains["mixed"].trace.items() if v is not None}
+    same = [all(np.array_equal(t64[k][c], tro[k][c], equal_nan=True)
+                for k in ("e_trial", "e_best", "e_best_acc", "e_cur", "step", "accepted"))
+            and np.array_equal(t64["e_cand"][c], tro["ecand"][c], equal_nan=True)
+            for c in range(sub)]
+    acc = tm["accepted"] == 1
+    xm = chains["mixed"].xyz_cur.cpu().numpy()
+    hm = {"xyz": xm, "energy": chains["mixed"].e_cur.cpu().numpy()}
+    entry["parity"] = {
+        "fp64_chain_bitwise_frac_subset": float(np.mean(same)), "fp64_subset_chains": sub,
+        "mixed_accepted_polish_converged_frac": float(np.mean(tm["polish_status"][acc] ==
+                                                              lj.CONVERGED)),
+        **{"mixed_current_" + k: v for k, v in errors_at_results(O, off, hm).items()}}
     return {w.name: entry}
+
+
+def candidate_sweep(O, cands=(1, 2, 4, 8, 16), steps=30, seed=2510):
+    """The paper's parallel scheme on the host (Parallel Evaluation of
+    Candidates; Figs. 4-5 in kind): one LJ38 chain with n candidates per step,
+    run twice for each n with the same random streams, once with the n
+    minimisations of a step in turn on one thread and once on a pool of
+    min(n, 16) worker threads with a barrier per step.  speedup = serial time
+    / pool time; efficiency = speedup / workers."""
+    import concurrent.futures as cf
+
+    from paper_2510_25938_amd.inputs import random_starts
+    off, x = random_starts([38], seed)
+    r0 = O.minimize(off, x)
+    one = np.array([0, 38], np.int32)
+
+    def run(n, workers):
+        params = O.bh_params(1, n, kT=0.8, seed=seed + n)
+        st = O.chain_state(float(r0["energy"][0]), 0.4)
+        xcur = r0["xyz"].copy()
+        with cf.ThreadPoolExecutor(workers) as ex:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                cand = [O.perturb(xcur, st.step, params.seed, 0, st.step_index, j)
+                        for j in range(n)]
+                res = list(ex.map(lambda c: O.minimize(one, c), cand))
+                sel, acc, _, _ = O.bh_decide(st, params, 0,
+                                             np.array([r["energy"][0] for r in res]))
+                if acc:
+                    xcur = res[sel]["xyz"]
+            return time.perf_counter() - t0, st.e_cur
+
+    rows = []
+    for n in cands:
+        P = max(1, min(n, pool_size()))
+        t1, e1 = run(n, 1)
+        tp, ep = run(n, P)
+        rows.append({"cands": n, "workers": P, "ms_per_step_serial": 1e3 * t1 / steps,
+                     "ms_per_step_pool": 1e3 * tp / steps, "speedup": t1 / tp,
+                     "efficiency": t1 / tp / P, "same_chain": bool(e1 == ep)})
+    return {"workload": f"one LJ38 chain, {steps} steps per candidate count, FP64 oracle",
+            "rows": rows}
 
 
 def mixed_result_errors(lj, O, batch, starts, params, off, hm, stream, torch):
@@ -461,6 +693,7 @@ def main():
                          f"pinned to core {core} ({cpu_s:.2f} s)", "cpu_model": cpu_model(),
                "host_cores": len(aff) if aff else os.cpu_count()}
         cpu["pool"] = oracle_pool(O, off, x, ro)
+        cpu["candidate_sweep"] = candidate_sweep(O)
         h64, hm = fp64["host"], mixed["host"]
         parity["fp64_bitwise_frac"] = float(np.mean(
             [np.array_equal(h64["xyz"][:, off[b]:off[b + 1]], ro["xyz"][:, off[b]:off[b + 1]])

@@ -6,6 +6,9 @@ scaling: the paper's candidate-count experiment (Results, Figs. 4-5): one
     energy, and speedup / efficiency relative to n = 1.  Many independent
     chains are run side by side (a batch of identical chains with different
     seeds) so the time to target is averaged over chains.
+    The default target is the chain's global minimum as computed from its
+    symmetric structure (LJ13 icosahedron -44.326801, LJ38 truncated
+    octahedron -173.928427).
 lj38: global search for LJ38 (Results, Fig. 6): many chains from random
     starts until one reaches the truncated-octahedral global minimum; the hit
     is confirmed by its energy (-173.928427, Wales & Doye 1997) and by the
@@ -22,6 +25,8 @@ import time
 import numpy as np
 
 LJ38_GLOBAL = -173.928427
+LJ13_GLOBAL = -44.326801
+GLOBAL_MINIMA = {13: LJ13_GLOBAL, 38: LJ38_GLOBAL}
 
 
 def _setup(n_atoms, chains, seed, torch, lj, inputs):
@@ -33,13 +38,22 @@ def _setup(n_atoms, chains, seed, torch, lj, inputs):
 
 
 def scaling(n_atoms=38, steps=200, chains=64, cands=(1, 2, 4, 8, 16, 32, 64), kT=0.8,
-            precision="mixed", target=None, seed=2510):
+            precision="mixed", target="global", seed=2510, traces=None):
     """Steps/s and time to target for one chain per candidate count (averaged over
-    `chains` independent chains run side by side)."""
+    `chains` independent chains run side by side).  target="global" uses the
+    computed global minimum of LJ13 or LJ38 (None: no target).  With `traces`
+    (a dict), the start minima and every candidate count's per-step trace are
+    stored in it."""
     import torch
 
     from . import inputs, lj
+    if target == "global":
+        target = GLOBAL_MINIMA.get(n_atoms)
     b, r = _setup(n_atoms, chains, seed, torch, lj, inputs)
+    if traces is not None:
+        traces["offset"] = b.offset_host
+        traces["xyz_min"] = r["xyz"].cpu().numpy()
+        traces["e_min"] = r["energy"].cpu().numpy()
     out = []
     stream = torch.cuda.Stream()
     for n in cands:
@@ -54,6 +68,9 @@ def scaling(n_atoms=38, steps=200, chains=64, cands=(1, 2, 4, 8, 16, 32, 64), kT
             stream.synchronize()
         ms = e0.elapsed_time(e1)
         best = ch.trace["e_best"].cpu().numpy()  # running lowest per chain and step
+        if traces is not None:
+            traces[n] = {k: v.cpu().numpy() for k, v in ch.trace.items() if v is not None}
+            traces[n]["seed"] = seed + n
         row = {"cands": n, "ms_per_step": ms / steps, "final_best_mean": float(best[:, -1].mean())}
         if target is not None:
             hit = best <= target + 1e-6
@@ -83,8 +100,11 @@ def o_h_shells(xyz):
     return bool(tight and gaps)
 
 
-def lj38(chains=512, cands=8, seconds=60.0, chunk=50, kT=0.8, precision="mixed", seed=38):
-    """Run many LJ38 chains until one finds the global minimum or time runs out."""
+def lj38(chains=512, cands=8, seconds=60.0, chunk=50, kT=0.8, precision="mixed", seed=38,
+         max_steps=None):
+    """Run many LJ38 chains until one finds the global minimum, time runs out or
+    max_steps steps are done.  On a hit, the result holds the chain, its best
+    structure (planes) and the O_h shell check."""
     import torch
 
     from . import inputs, lj
@@ -94,7 +114,7 @@ def lj38(chains=512, cands=8, seconds=60.0, chunk=50, kT=0.8, precision="mixed",
     t0 = time.perf_counter()
     steps = 0
     result = {"chains": chains, "cands": cands, "precision": precision, "found": False}
-    while time.perf_counter() - t0 < seconds:
+    while time.perf_counter() - t0 < seconds and (max_steps is None or steps < max_steps):
         ch.step(chunk)
         torch.cuda.synchronize()
         steps += chunk
@@ -104,7 +124,7 @@ def lj38(chains=512, cands=8, seconds=60.0, chunk=50, kT=0.8, precision="mixed",
         if best[k] <= LJ38_GLOBAL + 1e-6:
             off = b.offset_host
             xb = ch.xyz_best.cpu().numpy()[:, off[k]:off[k + 1]]
-            result.update(found=True, chain=k, o_h=o_h_shells(xb))
+            result.update(found=True, chain=k, o_h=o_h_shells(xb), xyz=xb.tolist())
             break
     return result
 
@@ -117,7 +137,8 @@ def main(argv=None):
     s.add_argument("--steps", type=int, default=200)
     s.add_argument("--chains", type=int, default=64)
     s.add_argument("--precision", default="mixed")
-    s.add_argument("--target", type=float, default=None)
+    s.add_argument("--target", default="global",
+                   help='"global" (computed LJ13 / LJ38 minimum), "none" or an energy')
     g = sub.add_parser("lj38")
     g.add_argument("--chains", type=int, default=512)
     g.add_argument("--cands", type=int, default=8)
@@ -125,12 +146,16 @@ def main(argv=None):
     g.add_argument("--precision", default="mixed")
     args = ap.parse_args(argv)
     if args.study == "scaling":
+        target = {"global": "global", "none": None}.get(args.target)
+        if target is None and args.target != "none":
+            target = float(args.target)
         for row in scaling(args.atoms, args.steps, args.chains, precision=args.precision,
-                           target=args.target):
+                           target=target):
             print(json.dumps(row), flush=True)
     else:
-        print(json.dumps(lj38(args.chains, args.cands, args.seconds, precision=args.precision)),
-              flush=True)
+        res = lj38(args.chains, args.cands, args.seconds, precision=args.precision)
+        res.pop("xyz", None)
+        print(json.dumps(res), flush=True)
     return 0
 
 
