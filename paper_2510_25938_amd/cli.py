@@ -2,14 +2,17 @@
 
     python -m paper_2510_25938_amd.cli input.molden [--steps 200] [--cands 8]
         [--kT 1.0] [--step0 0.4] [--precision fp64|mixed] [--seed S]
-        [--pair lj|morse] [--rho 6.0] [--sigma 1.0]
+        [--pair lj|morse] [--rho 6.0] [--sigma 1.0] [--trace steps.csv]
 
 Reads the first geometry of input.molden (Methodology, "Initial Structures
 and Input"), minimises it, runs the basin-hopping loop of the Algorithm
 Overview (perturb, n candidates minimised together, select, Metropolis,
 adapt every 10 steps toward 50 % acceptance) through lj_bh_step, and writes
 every accepted structure to input_accepted.molden (Running the Code).  Prints
-one line per step: trial energy, decision, lowest energy so far, step size.
+one line per step: the trial energy, the decision and the running lowest
+trial energy (the three series of Fig. 2), the lowest accepted energy so far
+(Fig. 3) and the step size.  --trace FILE also writes these series per step
+as CSV.
 """
 import argparse
 import os
@@ -41,6 +44,8 @@ def main(argv=None):
                     help="pair potential: Eq. (1) or the Morse pair (well depth 1 at r = 1)")
     ap.add_argument("--rho", type=float, default=6.0, help="Morse range")
     ap.add_argument("--quiet", action="store_true", help="no per-step lines")
+    ap.add_argument("--trace", default=None,
+                    help="write the per-step series (Figs. 2-3) to this CSV file")
     args = ap.parse_args(argv)
 
     import torch
@@ -60,18 +65,30 @@ def main(argv=None):
                       target_rate=args.target, seed=args.seed)
     chain = lj.BasinHopping(batch, r["xyz"], r["energy"], bh, params, args.precision,
                             step0=args.step0, trace_steps=args.steps)
-    frames, energies = [], []
+    frames, energies, rows = [], [], []
     for k in range(args.steps):
         chain.step(1)
         torch.cuda.synchronize()
-        acc = int(chain.trace["accepted"][0, k].item())
+        t = {key: chain.trace[key][0, k].item()
+             for key in ("e_trial", "accepted", "e_best", "e_best_acc", "e_cur", "step",
+                         "polish_status")}
+        acc = int(t["accepted"])
         if acc:
             frames.append(planes_to_aos(chain.xyz_cur.cpu().numpy()) * args.sigma)
             energies.append(float(chain.e_cur[0].item()))
+        rows.append((k + 1, t["e_trial"], acc, t["e_best"], t["e_best_acc"], t["e_cur"], t["step"],
+                     int(t["polish_status"])))
         if not args.quiet:
-            print(f"step {k + 1:5d}  E_trial {chain.trace['e_trial'][0, k].item():14.8f}  "
-                  f"{'accept' if acc else 'reject'}  E_low {chain.trace['e_best'][0, k].item():14.8f}"
-                  f"  s {chain.trace['step'][0, k].item():.5f}", flush=True)
+            print(f"step {k + 1:5d}  E_trial {t['e_trial']:14.8f}  "
+                  f"{'accept' if acc else 'reject'}  E_low {t['e_best']:14.8f}  "
+                  f"E_best_acc {t['e_best_acc']:14.8f}  s {t['step']:.5f}", flush=True)
+    if args.trace:
+        with open(args.trace, "w") as fh:
+            fh.write("step,e_trial,accepted,e_lowest_trial,e_best_accepted,e_current,step_size,"
+                     "polish_status\n")
+            for row in rows:
+                fh.write(f"{row[0]},{row[1]:.12f},{row[2]},{row[3]:.12f},{row[4]:.12f},"
+                         f"{row[5]:.12f},{row[6]:.10f},{row[7]}\n")
     out = os.path.splitext(args.molden)[0] + "_accepted.molden"
     write_geometries(out, frames, energies, syms)
     print(f"{len(frames)} accepted structures -> {out}; lowest accepted "

@@ -20,10 +20,19 @@ def test_cli_writes_accepted_structures(tmp_path):
     src = tmp_path / "lj13.molden"
     write_geometries(str(src), [planes_to_aos(x)], [0.0], ["Ar"] * 13)
     announce("cli lj13 30 steps")
+    trace = tmp_path / "trace.csv"
     out = subprocess.run([sys.executable, "-m", "paper_2510_25938_amd.cli", str(src), "--steps",
-                          "30", "--cands", "4", "--quiet"], capture_output=True, text=True,
-                         timeout=180)
+                          "30", "--cands", "4", "--quiet", "--trace", str(trace)],
+                         capture_output=True, text=True, timeout=180)
     assert out.returncode == 0, out.stderr
+    # the per-step series of Figs. 2-3: running lowest trial energy and lowest
+    # accepted energy never increase; accepted rows set the current energy
+    t = np.genfromtxt(trace, delimiter=",", names=True)
+    assert len(t) == 30 and np.all(np.diff(t["e_lowest_trial"]) <= 0)
+    assert np.all(np.diff(t["e_best_accepted"]) <= 0)
+    acc = t["accepted"] == 1
+    assert np.all(t["e_current"][acc] == t["e_trial"][acc])  # FP64: no polish
+    assert np.all(t["e_best_accepted"] <= t["e_current"])
     acc = tmp_path / "lj13_accepted.molden"
     text = acc.read_text()
     n_frames = text.count("E = ")
