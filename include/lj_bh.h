@@ -135,8 +135,12 @@ typedef struct {
     double gtol_mixed_per_atom; /* LJ_MIXED: FP32 phase ends at
                                    ||g|| < max(gtol, this*N)                    [1e-5] */
     int32_t polish;             /* LJ_MIXED: run the FP64 polish                [1]    */
-    double ls_noise;            /* LJ_MIXED: Armijo allowance for the full step
-                                   (alpha = 1), relative to |E|                 [5e-7] */
+    double ls_noise;            /* LJ_MIXED: FP32 energy resolution relative to
+                                   |E|: the Armijo allowance of the full step
+                                   near the FP32 tolerance, and the energy
+                                   change below which the FP32 phase judges a
+                                   trial by the slope test g_t.d <= (2c1-1) g.d
+                                                                                [5e-7] */
 } lj_lbfgs_params;
 
 void lj_lbfgs_defaults(lj_lbfgs_params* p);
