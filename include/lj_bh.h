@@ -289,23 +289,50 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
  *                      precision: w = 0 (16 wavefronts x 1 atom, the LJ_MIXED
  *                      default), 1 (8 x 2, the LJ_FP64 default) or 2 (4 x 4);
  *                      a is ignored.
+ *   LJ_SCHED_MIN_CLASS0..2  minimiser shape of the size class of 0..64,
+ *                      65..128 and 129..256 atoms (the cluster-per-workgroup
+ *                      schedule), keyed by precision, the class of max_n (the
+ *                      largest class in the batch) and the class's largest N
+ *                      rounded up to a power of two:
+ *                        class 0: w = 0 one cluster per wavefront, 1 one
+ *                                 cluster reduced over one 16-lane row
+ *                                 (N <= 16), 2 two clusters per wavefront
+ *                                 (N <= 32), 3 four clusters per wavefront
+ *                                 (N <= 16);
+ *                        class 1: w = 0 two wavefronts, 1 one wavefront with
+ *                                 two atoms per lane;
+ *                        class 2: w = 0 four wavefronts, 1 three wavefronts
+ *                                 (N <= 192).
+ *                      lj_set_schedule: w = -1 removes the entry (built-in
+ *                      rule); a is ignored.  lj_get_schedule: *w = the entry
+ *                      or -1 (none: the built-in rule, which for class 1 also
+ *                      depends on the cluster count), *a = its clusters per
+ *                      workgroup.
  * Results never depend on the schedule in LJ_FP64 (fixed summation order).
  */
 #define LJ_SCHED_EVAL 0
 #define LJ_SCHED_MIN_LARGE 1
+#define LJ_SCHED_MIN_CLASS0 2
+#define LJ_SCHED_MIN_CLASS1 3
+#define LJ_SCHED_MIN_CLASS2 4
 lj_status lj_set_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t w, int32_t a);
 lj_status lj_get_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_t* w, int32_t* a);
 
 /*
- * lj_autotune - time every candidate schedule for this batch shape and record
- * the fastest in the schedule table: all lj_energy_grad_batch shapes holding
- * max_n atoms (at most twice the padded size), and for max_n in 257..1024 the
+ * lj_autotune - time every candidate schedule for this batch and record the
+ * fastest in the schedule table: all lj_energy_grad_batch shapes holding
+ * max_n atoms (at most twice the padded size); for max_n in 257..1024 the
  * three large-cluster minimiser shapes (timed on a 3-iteration minimisation of
- * a copy of xyz).  xyz [3][total_atoms] is read only.  Unlike every other
- * call this one SYNCHRONISES the stream (it times launches with HIP events).
+ * a copy of xyz); then, for max_n <= 1024, the shapes of size classes 2, 1
+ * and 0 in turn, each timed on a whole minimisation of a copy of xyz (default
+ * parameters, at most 1000 iterations per phase) with the other classes at
+ * their current choice, a shape replacing the current one when at least 2 %
+ * faster.  xyz [3][total_atoms] is read only.  Unlike every other call this
+ * one SYNCHRONISES the stream (it times launches with HIP events).
  *   ws, ws_bytes     scratch of at least lj_autotune_workspace_bytes().
  *   best_eval_ms     fastest pair-kernel time (nullable).
- *   best_min_ms      fastest minimiser time, -1 if not tuned (nullable).
+ *   best_min_ms      minimisation time with the chosen shapes, -1 if not
+ *                    tuned (max_n above LJ_MAX_ATOMS_MIN) (nullable).
  */
 size_t lj_autotune_workspace_bytes(const lj_batch* batch, int32_t precision);
 lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precision, void* ws,

@@ -2,6 +2,7 @@
 // scheduling and the HIP-graph cache of the basin-hopping step.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -138,20 +139,64 @@ int large_schedule(int precision) {
     return g_large_sched[precision == LJ_MIXED ? 1 : 0];
 }
 
-// Workspace carve-up of one minimisation call.
+// Minimiser shapes of classes 0-2, filled by lj_autotune / lj_set_schedule:
+// (precision, class, largest class of the batch, power of two >= the class's
+// largest N) -> shape.
+std::map<std::array<int, 4>, int> g_class_sched;
+
+// The largest N that class c can hold in a batch whose largest N is max_n.
+int class_cap(int c, int max_n) {
+    const int cap = lj::kClassMaxN[c];
+    return max_n < cap ? (max_n < 0 ? 0 : max_n) : cap;
+}
+
+std::array<int, 4> class_key(int precision, int c, int max_n) {
+    return {precision == LJ_MIXED ? 1 : 0, c, lj::class_of(max_n < 0 ? 0 : max_n),
+            pow2_at_least(class_cap(c, max_n) < 1 ? 1 : class_cap(c, max_n))};
+}
+
+// Built-in rule for the shape of class c (0-2).
+int default_class_shape(int c, int max_n, int top_class, int mixed, int num, int cus) {
+    const int cmax = class_cap(c, max_n);
+    if (c == 0) return cmax <= 16 ? 1 : 0;  // one 16-lane row
+    if (c == 2) return cmax <= 192 ? 1 : 0; // three wavefronts
+    // Class 1 as one wavefront with two atoms per lane: about 1.5 times the
+    // time per iteration of two wavefronts, but one SIMD per team instead of
+    // two, so twice the teams drain the class.  That wins when the class
+    // shares the call with larger clusters, and on the FP64 path when the
+    // batch has at least one cluster per SIMD; otherwise the slowest cluster
+    // decides and two wavefronts are faster (mixed-path registers spill more
+    // in the one-wavefront form).
+    return (top_class >= 2 || (!mixed && num >= 4 * cus)) ? 1 : 0;
+}
+
+int class_schedule(int precision, int c, int max_n, int num, int cus) {
+    const int top = lj::class_of(max_n < 0 ? 0 : max_n);
+    if (c == 3) return large_schedule(precision);
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        auto it = g_class_sched.find(class_key(precision, c, max_n));
+        if (it != g_class_sched.end() && lj::shape_max_n(c, it->second) >= class_cap(c, max_n))
+            return it->second;
+    }
+    return default_class_shape(c, max_n, top, precision == LJ_MIXED, num, cus);
+}
+
+// Workspace carve-up of one minimisation call, and the shape of each class.
 struct MinLayout {
     size_t list = 0, cls = 0, queue = 0, hist = 0, total = 0;
     int top_class = -1;
-    int large = 0;
-    bool narrow[lj::kNumClasses] = {false, false, false, false};  // see minimize_kernel_for
+    int shape[lj::kNumClasses] = {0, 0, 0, 0};
     int grid[lj::kNumClasses] = {0, 0, 0, 0};
 };
 
-lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int large = -1) {
+// force (nullable): a shape per class, -1 for the schedule table's choice.
+lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L,
+                     const int* force = nullptr) {
     DeviceInfo di;
     lj_status s = device_info(di);
     if (s != LJ_OK) return s;
-    L.large = large >= 0 ? large : large_schedule(mixed ? LJ_MIXED : LJ_FP64);
+    const int prec = mixed ? LJ_MIXED : LJ_FP64;
     size_t off = 0;
     L.list = off;
     off = align_up(off + sizeof(int32_t) * (size_t)(num > 0 ? num : 1));
@@ -159,38 +204,36 @@ lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L, int l
     off = align_up(off + sizeof(int32_t) * 2 * lj::kNumClasses);
     L.queue = off;
     off = align_up(off + sizeof(int32_t) * lj::kNumClasses);
-    L.top_class = lj::class_of(max_n < 0 ? 0 : max_n);
     // the plan rejects clusters above max_n, so max_n bounds every class
-    L.narrow[0] = max_n <= 16;
-    L.narrow[2] = max_n <= 192;
-    // The 65-128-atom class as one wavefront with two atoms per lane: about 1.5
-    // times the time per iteration of two wavefronts, but one SIMD per team
-    // instead of two, so twice the teams drain the class.  That wins when the
-    // class shares the call with larger clusters, and on the FP64 path when
-    // the batch has at least one cluster per SIMD; otherwise the slowest
-    // cluster decides and two wavefronts are faster (mixed-path registers
-    // spill more in the one-wavefront form).
-    L.narrow[1] = L.top_class >= 2 || (!mixed && num >= 4 * di.cus);
-    auto grid_for = [&](int c, int large_shape, int& g_out) -> lj_status {
+    L.top_class = lj::class_of(max_n < 0 ? 0 : max_n);
+    for (int c = 0; c <= L.top_class; ++c) {
+        L.shape[c] = (force && force[c] >= 0) ? force[c] : class_schedule(prec, c, max_n, num, di.cus);
+        if (L.shape[c] < 0 || L.shape[c] >= lj::class_shapes(c) ||
+            lj::shape_max_n(c, L.shape[c]) < class_cap(c, max_n))
+            return fail(LJ_E_ARG, "minimiser shape %d of class %d does not hold %d atoms",
+                        L.shape[c], c, class_cap(c, max_n));
+    }
+    auto grid_for = [&](int c, int shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, lj::minimize_kernel_for(mixed, pot, c, large_shape, L.narrow[c]),
-            lj::class_block(c, large_shape, L.narrow[c]), 0));
+            &per_cu, lj::minimize_kernel_for(mixed, pot, c, shape), lj::class_block(c, shape), 0));
         if (per_cu < 1) per_cu = 1;
+        const int per_wg = lj::shape_clusters_per_wg(c, shape);
         long g = (long)per_cu * di.cus;
-        if (g > num) g = num;
+        const long need = ((long)num + per_wg - 1) / per_wg;
+        if (g > need) g = need;
         if (g < 1) g = 1;
         g_out = (int)g;
         return LJ_OK;
     };
     for (int c = 0; c <= L.top_class; ++c)
-        if ((s = grid_for(c, L.large, L.grid[c])) != LJ_OK) return s;
+        if ((s = grid_for(c, L.shape[c], L.grid[c])) != LJ_OK) return s;
     L.hist = off;
     if (L.top_class >= 3) {
         // sized for the largest grid of any large-cluster shape, so a workspace
         // stays valid whichever shape the schedule table selects
         size_t hist = 0;
-        for (int k = 0; k < lj::kNumLargeShapes; ++k) {
+        for (int k = 0; k < lj::class_shapes(3); ++k) {
             int g = 0;
             if ((s = grid_for(3, k, g)) != LJ_OK) return s;
             const size_t b = lj::class_hist_bytes_per_wg(3, k) * (size_t)g;
@@ -273,7 +316,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     if (L.top_class == 0) {
         a.cls = 0;
         a.hist = nullptr;
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, 0, L.large, L.narrow[0], L.grid[0], a, st));
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, 0, L.shape[0], L.grid[0], a, st));
         return LJ_OK;
     }
     // several size classes: run them concurrently on side streams
@@ -286,7 +329,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
         for (int c = L.top_class; c >= 0; --c) {
             a.cls = c;
             a.hist = (c == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
-            LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.narrow[c], L.grid[c], a, st));
+            LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.shape[c], L.grid[c], a, st));
         }
         return LJ_OK;
     }
@@ -299,15 +342,14 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     // took 60 instead of 47 ms that way).
     a.cls = L.top_class;
     a.hist = (L.top_class == 3) ? reinterpret_cast<double*>(ws + L.hist) : nullptr;
-    LJ_HIP_TRY(lj::launch_minimize_class(mixed, L.top_class, L.large, L.narrow[L.top_class],
+    LJ_HIP_TRY(lj::launch_minimize_class(mixed, L.top_class, L.shape[L.top_class],
                                          L.grid[L.top_class], a, st));
     a.hist = nullptr;
     for (int c = L.top_class - 1; c >= 0; --c) {
         const int k = L.top_class - 1 - c;
         a.cls = c;
         LJ_HIP_TRY(hipStreamWaitEvent(ss->s[k], ss->fork, 0));
-        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.large, L.narrow[c], L.grid[c], a,
-                                             ss->s[k]));
+        LJ_HIP_TRY(lj::launch_minimize_class(mixed, c, L.shape[c], L.grid[c], a, ss->s[k]));
         LJ_HIP_TRY(hipEventRecord(ss->join[k], ss->s[k]));
     }
     for (int k = 0; k < L.top_class; ++k) LJ_HIP_TRY(hipStreamWaitEvent(st, ss->join[k], 0));
@@ -441,7 +483,7 @@ void key_add(std::vector<unsigned char>& k, const T& v) {
 std::vector<unsigned char> step_key(const lj_batch* ch, const lj::BhStateDev& sd,
                                     const lj::BhDev& pd, const lj_lbfgs_params* lp,
                                     int32_t precision, const lj::BhTraceDev& td, const void* ws,
-                                    size_t ws_bytes, hipStream_t st) {
+                                    size_t ws_bytes, hipStream_t st, const BhLayout& L) {
     std::vector<unsigned char> k;
     k.reserve(320);
     key_add(k, ch->num);
@@ -481,11 +523,12 @@ std::vector<unsigned char> step_key(const lj_batch* ch, const lj::BhStateDev& sd
     key_add(k, ws);
     key_add(k, ws_bytes);
     key_add(k, st);
-    // a graph keeps the launch shapes it captured: the candidates' schedule
-    // and, on the mixed path, the FP64 schedule of the accepted candidates'
-    // polish
-    key_add(k, large_schedule(precision));
-    key_add(k, large_schedule(LJ_FP64));
+    // a graph keeps the launch shapes it captured: the candidates' minimiser
+    // shapes and, on the mixed path, those of the accepted candidates' polish
+    for (int c = 0; c < lj::kNumClasses; ++c) {
+        key_add(k, L.cand_min.shape[c]);
+        key_add(k, L.polish_min.shape[c]);
+    }
     return k;
 }
 
@@ -702,7 +745,7 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
     int dev = 0;
     LJ_HIP_TRY(hipGetDevice(&dev));
     const std::vector<unsigned char> key =
-        step_key(chains, sd, pd, params, precision, td, ws, ws_bytes, st);
+        step_key(chains, sd, pd, params, precision, td, ws, ws_bytes, st, L);
     // Graphs are launched with the cache locked, so another thread's insertion
     // cannot evict and destroy a graph between its lookup and its launch.
     {
@@ -766,6 +809,24 @@ lj_status lj_set_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_
         g_large_sched[precision == LJ_MIXED ? 1 : 0] = w;
         return LJ_OK;
     }
+    if (kind >= LJ_SCHED_MIN_CLASS0 && kind <= LJ_SCHED_MIN_CLASS2) {
+        const int c = kind - LJ_SCHED_MIN_CLASS0;
+        if (max_n < 0 || max_n > LJ_MAX_ATOMS_MIN) return fail(LJ_E_ARG, "max_n out of range");
+        if (lj::class_of(max_n) < c)
+            return fail(LJ_E_ARG, "a batch of at most %d atoms has no class-%d clusters", max_n, c);
+        if (w == -1) {  // back to the built-in rule
+            std::lock_guard<std::mutex> lk(g_sched_mu);
+            g_class_sched.erase(class_key(precision, c, max_n));
+            return LJ_OK;
+        }
+        if (w < 0 || w >= lj::class_shapes(c)) return fail(LJ_E_ARG, "class-%d shape %d", c, w);
+        if (lj::shape_max_n(c, w) < class_cap(c, max_n))
+            return fail(LJ_E_ARG, "class-%d shape %d holds at most %d atoms, not %d", c, w,
+                        lj::shape_max_n(c, w), class_cap(c, max_n));
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_class_sched[class_key(precision, c, max_n)] = w;
+        return LJ_OK;
+    }
     return fail(LJ_E_ARG, "unknown schedule kind %d", kind);
 }
 
@@ -784,6 +845,15 @@ lj_status lj_get_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_
         *a = 0;
         return LJ_OK;
     }
+    if (kind >= LJ_SCHED_MIN_CLASS0 && kind <= LJ_SCHED_MIN_CLASS2) {
+        const int c = kind - LJ_SCHED_MIN_CLASS0;
+        if (max_n < 0 || max_n > LJ_MAX_ATOMS_MIN) return fail(LJ_E_ARG, "max_n out of range");
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        auto it = g_class_sched.find(class_key(precision, c, max_n));
+        *w = it == g_class_sched.end() ? -1 : it->second;
+        *a = *w < 0 ? 0 : lj::shape_clusters_per_wg(c, *w);
+        return LJ_OK;
+    }
     return fail(LJ_E_ARG, "unknown schedule kind %d", kind);
 }
 
@@ -791,7 +861,7 @@ size_t lj_autotune_workspace_bytes(const lj_batch* batch, int32_t precision) {
     if (check_batch(batch, LJ_MAX_ATOMS_EVAL, "lj_autotune_workspace_bytes") != LJ_OK) return 0;
     size_t off = align_up(sizeof(double) * (size_t)(batch->num > 0 ? batch->num : 1));  // energy
     off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);              // grad
-    if (batch->max_n > 256 && batch->max_n <= LJ_MAX_ATOMS_MIN) {
+    if (batch->max_n <= LJ_MAX_ATOMS_MIN) {
         off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);  // xyz copy
         off = align_up(off + 5 * sizeof(double) * (size_t)batch->num);          // outputs
         MinLayout L;
@@ -877,9 +947,14 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
         g_eval_sched[{precision, pow2_at_least(need_slots)}] = best_shape;
     }
     if (best_eval_ms) *best_eval_ms = best_ms;
-    // large-cluster minimiser: a 3-iteration minimisation of a copy per shape
+    // Minimiser shapes (batches of at most LJ_MAX_ATOMS_MIN atoms): the
+    // large-cluster class on a 3-iteration minimisation of a copy per shape;
+    // then classes 2, 1, 0 in turn, each shape on a whole minimisation of a
+    // copy (at most 1000 iterations per phase) with the other classes at their
+    // current choice.  A shape replaces the current one when it is at least
+    // 2 % faster; the choices go into the schedule table.
     float best_min = -1.f;
-    if (s == LJ_OK && batch->max_n > 256 && batch->max_n <= LJ_MAX_ATOMS_MIN) {
+    if (s == LJ_OK && batch->max_n <= LJ_MAX_ATOMS_MIN) {
         double* xc = reinterpret_cast<double*>(w + off);
         off = align_up(off + sizeof(double) * 3 * (size_t)batch->total_atoms);
         double* outs = reinterpret_cast<double*>(w + off);
@@ -887,31 +962,79 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
         int32_t* it = reinterpret_cast<int32_t*>(outs + 2 * (size_t)batch->num);
         int32_t* ev = it + batch->num;
         int32_t* stt = ev + batch->num;
+        MinLayout base;
+        if ((s = min_layout(batch->num, batch->max_n, mixed, batch->pair, base)) != LJ_OK)
+            return s;
+        int chosen[lj::kNumClasses] = {-1, -1, -1, -1};
+        for (int c = 0; c <= base.top_class; ++c) chosen[c] = base.shape[c];
         lj_lbfgs_params lp;
         lj_lbfgs_defaults(&lp);
-        lp.max_iter = 3;
-        lp.polish = 0;
-        int best_k = 0;
-        best_min = 1e30f;
-        for (int k = 0; k < lj::kNumLargeShapes && s == LJ_OK; ++k) {
+        auto time_shapes = [&](const int* force, const lj_lbfgs_params& prm, float& ms) -> lj_status {
             MinLayout L;
-            if ((s = min_layout(batch->num, batch->max_n, mixed, batch->pair, L, k)) != LJ_OK) break;
-            float ms = 0.f;
-            s = time_it([&]() -> lj_status {
+            lj_status r = min_layout(batch->num, batch->max_n, mixed, batch->pair, L, force);
+            if (r != LJ_OK) return r;
+            return time_it([&]() -> lj_status {
                 LJ_HIP_TRY(hipMemcpyAsync(xc, xyz, sizeof(double) * 3 * (size_t)batch->total_atoms,
                                           hipMemcpyDeviceToDevice, st));
                 return enqueue_minimize(batch, nullptr, xc, outs, outs + batch->num, it, ev, stt,
-                                        nullptr, to_dev(&lp), mixed, L, w + off, st);
+                                        nullptr, to_dev(&prm), mixed, L, w + off, st);
             }, ms);
-            if (s == LJ_OK && ms < best_min) {
-                best_min = ms;
-                best_k = k;
+        };
+        if (base.top_class >= 3) {
+            lj_lbfgs_params lp3 = lp;
+            lp3.max_iter = 3;
+            lp3.polish = 0;
+            float best3 = 1e30f;
+            for (int k = 0; k < lj::class_shapes(3) && s == LJ_OK; ++k) {
+                int force[lj::kNumClasses];
+                for (int c = 0; c < lj::kNumClasses; ++c) force[c] = chosen[c];
+                force[3] = k;
+                float ms = 0.f;
+                s = time_shapes(force, lp3, ms);
+                if (s == LJ_OK && ms < best3) {
+                    best3 = ms;
+                    chosen[3] = k;
+                }
+            }
+            if (s == LJ_OK) {
+                std::lock_guard<std::mutex> lk(g_sched_mu);
+                g_large_sched[mixed] = chosen[3];
             }
         }
+        lp.max_iter = 1000;
+        float cur = 0.f;
+        if (s == LJ_OK) s = time_shapes(chosen, lp, cur);
+        // the class sizes of this batch, from the plan of the last timed call
+        int32_t counts[2 * lj::kNumClasses] = {0};
         if (s == LJ_OK) {
-            std::lock_guard<std::mutex> lk(g_sched_mu);
-            g_large_sched[mixed] = best_k;
+            MinLayout L;
+            if ((s = min_layout(batch->num, batch->max_n, mixed, batch->pair, L, chosen)) != LJ_OK)
+                return s;
+            LJ_HIP_TRY(hipMemcpyAsync(counts, w + off + L.cls, sizeof(counts),
+                                      hipMemcpyDeviceToHost, st));
+            LJ_HIP_TRY(hipStreamSynchronize(st));
         }
+        for (int c = base.top_class < 2 ? base.top_class : 2; c >= 0 && s == LJ_OK; --c) {
+            if (counts[lj::kNumClasses + c] == 0) continue;  // no cluster of this class
+            const int cap = class_cap(c, batch->max_n);
+            for (int k = 0; k < lj::class_shapes(c) && s == LJ_OK; ++k) {
+                if (k == chosen[c] || lj::shape_max_n(c, k) < cap) continue;
+                int force[lj::kNumClasses];
+                for (int q = 0; q < lj::kNumClasses; ++q) force[q] = chosen[q];
+                force[c] = k;
+                float ms = 0.f;
+                s = time_shapes(force, lp, ms);
+                if (s == LJ_OK && ms < 0.98f * cur) {
+                    cur = ms;
+                    chosen[c] = k;
+                }
+            }
+            if (s == LJ_OK) {
+                std::lock_guard<std::mutex> lk(g_sched_mu);
+                g_class_sched[class_key(precision, c, batch->max_n)] = chosen[c];
+            }
+        }
+        if (s == LJ_OK) best_min = cur;
     }
     if (best_min_ms) *best_min_ms = best_min;
     return s;

@@ -106,6 +106,42 @@ __device__ __forceinline__ double wave_sum(double v) {
     return a + b;
 }
 
+// G clusters packed in one wavefront (G = 2: lanes 32k .. 32k + 31; G = 4:
+// one 16-lane row each): the sum over each cluster's lanes, in the pairwise
+// order over its lane index.  The four row levels of wave_sum give each row's
+// 16-leaf tree; for G = 2 the permlane16 swap then pairs rows 0 with 1 and 2
+// with 3.  Every lane ends with its own cluster's sum.  These are the trees
+// the pairwise sum pads N <= 16 (G = 4) or N <= 32 (G = 2) to.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(G == 2 || G == 4, "2 or 4 clusters per wavefront");
+    v = v + dpp<kDppXor1>(v);
+    v = v + dpp<kDppXor2>(v);
+    v = v + dpp<kDppHalfMirror>(v);
+    v = v + dpp<kDppMirror>(v);
+    if constexpr (G == 2) {
+        double a, b;
+        swap_rows16(v, a, b);
+        v = a + b;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double group_max(double v) {
+    static_assert(G == 2 || G == 4, "2 or 4 clusters per wavefront");
+    v = fmax(v, dpp<kDppXor1>(v));
+    v = fmax(v, dpp<kDppXor2>(v));
+    v = fmax(v, dpp<kDppHalfMirror>(v));
+    v = fmax(v, dpp<kDppMirror>(v));
+    if constexpr (G == 2) {
+        double a, b;
+        swap_rows16(v, a, b);
+        v = fmax(a, b);
+    }
+    return v;
+}
+
 constexpr int kDppRor4 = 0x124;   // row_ror:4  (lane i of a row takes lane i - 4)
 constexpr int kDppRor8 = 0x128;   // row_ror:8  (i takes i ^ 8)
 constexpr int kDppRor12 = 0x12C;  // row_ror:12 (i takes i + 4)
@@ -430,11 +466,11 @@ __device__ __forceinline__ void pair_morse32(const float4 p, bool self, float xi
 constexpr int kGroup64 = 4;
 constexpr int kGroup32 = 8;
 
+// t: the atom index of this thread's slot 0 (atom a T + t is slot a).
 template <int A, int T, int POT, bool IEEE = true>
 __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ pos,
                                            const double (&x)[3][A], double (&e)[A],
-                                           double (&g)[3][A], double rho) {
-    const int t = threadIdx.x;
+                                           double (&g)[3][A], double rho, int t) {
     const double c = -2.0 * rho;
     // 24 and -48 held in registers for the whole loop: a 64-bit constant that
     // is not an inline one would otherwise be rebuilt by two moves per pair
@@ -476,8 +512,7 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
 template <int A, int T, int POT>
 __device__ __forceinline__ void pairs_mixed(int n, const float4* __restrict__ pos,
                                             const double (&x)[3][A], double (&e)[A],
-                                            double (&g)[3][A], double rho) {
-    const int t = threadIdx.x;
+                                            double (&g)[3][A], double rho, int t) {
     const float rf = (float)rho, cf = -2.0f * rf;
     float xf[3][A];
 #pragma unroll

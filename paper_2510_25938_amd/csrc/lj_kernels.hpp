@@ -62,19 +62,20 @@ bool eval_shape_supported(EvalShape s);
 hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const int32_t* off,
                               int64_t total, const double* xyz, double* e, double* g, double rho,
                               hipStream_t st);
+// Minimiser shapes per size class (see lj_minimize.hip): class_shapes(c)
+// interchangeable kernels; shape s holds clusters of at most
+// shape_max_n(c, s) atoms, shape_clusters_per_wg(c, s) of them per workgroup.
 int class_of(int n);
-int class_block(int c, int large, bool narrow);
-size_t class_hist_bytes_per_wg(int c, int large);
-// narrow selects a leaner kernel for class c.  Class 0: every cluster has at
-// most 16 atoms (reductions over one 16-lane row).  Class 2: at most 192 atoms
-// (three wavefronts).  Class 1: larger classes share the call, or an FP64
-// batch has a cluster per SIMD (one wavefront with two atoms per lane, so a
-// team needs one SIMD instead of two).
-const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool narrow);
+int class_shapes(int c);
+int shape_max_n(int c, int shape);
+int shape_clusters_per_wg(int c, int shape);
+int class_block(int c, int shape);
+size_t class_hist_bytes_per_wg(int c, int shape);
+const void* minimize_kernel_for(int mixed, int pot, int c, int shape);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st);
-hipError_t launch_minimize_class(int mixed, int c, int large, bool narrow, int grid,
-                                 const MinArgs& a, hipStream_t st);
+hipError_t launch_minimize_class(int mixed, int c, int shape, int grid, const MinArgs& a,
+                                 hipStream_t st);
 
 struct BhDev {
     int cands;

@@ -19,26 +19,52 @@
 namespace lj {
 
 // ---------------------------------------------------------------------------
-// Team: LDS buffers and the collective operations of one workgroup.
+// Team: LDS buffers and the collective operations of one workgroup, or (G > 1)
+// of one of the G clusters packed in a one-wavefront workgroup, each on its
+// own 64 / G lanes.  A packed team's values are uniform over its lanes only,
+// so its reductions stay within those lanes and nothing is read out as a
+// wavefront-uniform scalar; LDS order within one wavefront needs no barrier
+// (a wavefront's LDS instructions execute in issue order).
 // ---------------------------------------------------------------------------
-template <int W, int A, int POT, int L = kWave>
+template <int W, int A, int POT, int L = kWave, int G = 1>
 struct Team {
+    static_assert(G == 1 || (W == 1 && A == 1 && L == kWave), "packing: one wavefront, one slot");
     static constexpr int T = kWave * W;
     static constexpr int NVMAX = 4 * A;
-    double4* pos64;
+    static constexpr int kG = G;
+    double4* pos64;  // this team's atoms (a packed team: its own part of the buffer)
     float4* pos32;
     float* rbuf;  // reaction buffers of the FP32 tiles and the one-wavefront ring
     TeamScratch<W, NVMAX>* sc;
     int bank;
     int n;
+    int li;      // atom index of this thread's slot 0 within the cluster
     double rho;  // Morse range (POT == kPairMorse)
 
-    __device__ __forceinline__ bool active(int a) const { return a * T + (int)threadIdx.x < n; }
+    __device__ __forceinline__ bool active(int a) const { return a * T + li < n; }
+
+    // a value uniform over the team, as the team's scalar
+    __device__ __forceinline__ int uni(int v) const {
+        if constexpr (G > 1)
+            return v;
+        else
+            return uniform(v);
+    }
+
+    __device__ __forceinline__ void sync() const {
+        if constexpr (G > 1) {
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    }
 
     __device__ __forceinline__ double dot(const double (&u)[3][A], const double (&v)[3][A]) {
         double p[1][A], o[1];
 #pragma unroll
         for (int a = 0; a < A; ++a) p[0][a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
+        if constexpr (G > 1) return group_sum<G>(p[0][0]);
         team_sum<W, A, 1, NVMAX, L>(p, o, *sc, bank);
         return o[0];
     }
@@ -55,7 +81,12 @@ struct Team {
             p[2][a] = fma(s[2][a], s[2][a], fma(s[1][a], s[1][a], s[0][a] * s[0][a]));
             p[3][a] = fma(w[2][a], w[2][a], fma(w[1][a], w[1][a], w[0][a] * w[0][a]));
         }
-        team_sum<W, A, 4, NVMAX, L>(p, o, *sc, bank);
+        if constexpr (G > 1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] = group_sum<G>(p[k][0]);
+        } else {
+            team_sum<W, A, 4, NVMAX, L>(p, o, *sc, bank);
+        }
         sy = o[0];
         yy = o[1];
         ss = o[2];
@@ -67,6 +98,7 @@ struct Team {
         double m[A];
 #pragma unroll
         for (int a = 0; a < A; ++a) m[a] = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
+        if constexpr (G > 1) return group_max<G>(m[0]);
         return team_max<W, A, NVMAX, L>(m, *sc, bank);
     }
 
@@ -84,6 +116,13 @@ struct Team {
             p[a] = fma(u[2][a], v[2][a], fma(u[1][a], v[1][a], u[0][a] * v[0][a]));
             const double n2 = fma(v[2][a], v[2][a], fma(v[1][a], v[1][a], v[0][a] * v[0][a]));
             m = a == 0 ? n2 : fmax(m, n2);
+        }
+        if constexpr (G > 1) {
+            // a packed team: any value <= cap2 serves when no atom of the
+            // wavefront exceeds cap2
+            uv = group_sum<G>(p[0]);
+            vmax2 = __builtin_amdgcn_ballot_w64(m > cap2) != 0 ? group_max<G>(m) : 0.0;
+            return;
         }
 #pragma unroll
         for (int a = 0; a < A; ++a) ws[a] = wave_sum<L>(p[a]);
@@ -126,15 +165,15 @@ struct Team {
     // the Morse pair (e_i holds V).
     template <bool F32>
     __device__ __forceinline__ double eval(const double (&x)[3][A], double (&g)[3][A]) {
-        constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A>;
-        constexpr bool kRing = F32 && W == 1 && A == 1;
+        constexpr bool kTiles = F32 && POT == kPairLJ && kUseTiles<W, A> && G == 1;
+        constexpr bool kRing = F32 && W == 1 && A == 1 && G == 1;
         bool ring = false, tiles = false;
         if constexpr (kRing) ring = ring_for(n);
         if constexpr (kTiles) tiles = !ring && tiles_for(n);
-        __syncthreads();  // previous readers of the position and reaction buffers are done
+        sync();  // previous readers of the position and reaction buffers are done
 #pragma unroll
         for (int a = 0; a < A; ++a) {
-            const int i = a * T + threadIdx.x;
+            const int i = a * T + li;
             if (ring) {  // ring layout: pos[j] = atom j mod n for j < 64 + steps
                 if (i < n) {
                     const float4 p = make_float4((float)x[0][a], (float)x[1][a], (float)x[2][a],
@@ -157,34 +196,41 @@ struct Team {
                     pos64[i] = make_double4(x[0][a], x[1][a], x[2][a], 0.0);
             }
         }
-        __syncthreads();
+        sync();
         double e[1][A], o[1];
         if (ring) {
             if constexpr (kRing) pairs_ring<POT>(n, pos32, rbuf, e[0][0], g, rho);
         } else if (tiles) {
             if constexpr (kTiles) pairs_tiles<W, A>(n, pos32, rbuf, e[0], g);
         } else if constexpr (F32) {
-            pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho);
+            pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho, li);
         } else {
-            pairs_fp64<A, T, POT, POT == kPairMorse>(n, pos64, x, e[0], g, rho);
+            pairs_fp64<A, T, POT, POT == kPairMorse>(n, pos64, x, e[0], g, rho, li);
         }
 #pragma unroll
         for (int a = 0; a < A; ++a)
             if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
-        team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
+        sum_energy(e, o);
         if constexpr (!F32 && POT == kPairLJ) {
             // only a pair distance outside the range of recip_in_range can make
             // 1/r2 differ from the IEEE quotient, and it makes E not finite:
             // then the evaluation is repeated with the IEEE division
             if (!isfinite(o[0])) {
-                pairs_fp64<A, T, POT, true>(n, pos64, x, e[0], g, rho);
+                pairs_fp64<A, T, POT, true>(n, pos64, x, e[0], g, rho, li);
 #pragma unroll
                 for (int a = 0; a < A; ++a)
                     if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
-                team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
+                sum_energy(e, o);
             }
         }
         return (POT == kPairMorse ? 0.5 : 2.0) * o[0];
+    }
+
+    __device__ __forceinline__ void sum_energy(double (&e)[1][A], double (&o)[1]) {
+        if constexpr (G > 1)
+            o[0] = group_sum<G>(e[0][0]);
+        else
+            team_sum<W, A, 1, NVMAX, L>(e, o, *sc, bank);
     }
 };
 
@@ -264,7 +310,7 @@ struct History<W, A, true> {
     // r <- H r (r holds g on entry).
     template <class TM>
     __device__ __forceinline__ void apply(TM& tm, double (&r)[3][A]) {
-        const int h = uniform(hist);
+        const int h = tm.uni(hist);
         if (h == kMaxM) {
             apply_full(tm, r);
             return;
@@ -344,7 +390,7 @@ struct History<W, A, false> {
 
     template <class TM>
     __device__ __forceinline__ void apply(TM& tm, double (&r)[3][A]) {
-        const int h = uniform(hist);
+        const int h = tm.uni(hist);
         double al[kMaxM];
         double v[3][A];
 #pragma unroll
@@ -405,8 +451,8 @@ constexpr double kNoiseZone = 100.0;
 constexpr int kZonePatience = 30;
 
 // E and g at x with FP32 pair arithmetic when f32 (only compiled when CAN32).
-template <bool CAN32, int W, int A, int POT, int L>
-__device__ __forceinline__ double eval_phase(Team<W, A, POT, L>& tm, const double (&x)[3][A],
+template <bool CAN32, int W, int A, int POT, int L, int G>
+__device__ __forceinline__ double eval_phase(Team<W, A, POT, L, G>& tm, const double (&x)[3][A],
                                              double (&g)[3][A], bool f32) {
     if constexpr (CAN32) {
         if (f32) return tm.template eval<true>(x, g);
@@ -419,8 +465,8 @@ __device__ __forceinline__ double eval_phase(Team<W, A, POT, L>& tm, const doubl
 // single copy of this loop for both phases) selects the FP32 pair arithmetic,
 // the Armijo noise allowance and the stall exit of the mixed path's first
 // phase.
-template <bool CAN32, int W, int A, bool HREG, int POT, int L>
-__device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double (&x)[3][A],
+template <bool CAN32, int W, int A, bool HREG, int POT, int L, int G>
+__device__ int lbfgs_run(Team<W, A, POT, L, G>& tm, History<W, A, HREG>& H, double (&x)[3][A],
                          double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
                          const LbfgsDev& p, double gtol, int max_iter, bool f32_flag) {
     const bool F32 = CAN32 && f32_flag;
@@ -460,7 +506,7 @@ __device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double 
             for (int a = 0; a < A; ++a) d[c][a] = -d[c][a];
         double gd, dmax2;
         tm.dot_max(g, d, gd, dmax2, ms2);
-        if (uniform(H.hist) > 0 && !(gd < 0.0)) {
+        if (tm.uni(H.hist) > 0 && !(gd < 0.0)) {
             H.clear();
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -520,7 +566,7 @@ __device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double 
         // dropped for a steepest-descent restart
         if (ok && F32 && E > 0.0 && !(E - Et > p.ls_noise * E)) ok = false;
         if (!ok) {
-            if (uniform(H.hist) > 0) {
+            if (tm.uni(H.hist) > 0) {
                 H.clear();
                 continue;
             }
@@ -545,7 +591,7 @@ __device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double 
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int a = 0; a < A; ++a) g[c][a] = gt[c][a];
-            if (uniform(H.hist) > 0) {
+            if (tm.uni(H.hist) > 0) {
                 H.clear();
                 continue;
             }
@@ -587,21 +633,28 @@ __device__ int lbfgs_run(Team<W, A, POT, L>& tm, History<W, A, HREG>& H, double 
 }
 
 // ---------------------------------------------------------------------------
-// Persistent minimiser kernel: one launch per size class.
+// Persistent minimiser kernel: one launch per size class.  A workgroup claims
+// the next cluster of its class from the queue (G > 1: the next G clusters,
+// one per packed team of 64 / G lanes) and minimises it; it claims again once
+// all of its teams are done.
 // ---------------------------------------------------------------------------
-template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave>
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1>
 __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     constexpr int T = kWave * W;
+    constexpr int LG = kWave / G;  // lanes of a packed team
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
     __shared__ int claim;
-    __shared__ float tile_rbuf[(MIXED && ((POT == kPairLJ && kUseTiles<W, A>) || (W == 1 && A == 1)))
+    __shared__ float tile_rbuf[(MIXED && G == 1 &&
+                                ((POT == kPairLJ && kUseTiles<W, A>) || (W == 1 && A == 1)))
                                    ? 6 * T * A
                                    : 1];
 
-    Team<W, A, POT, L> tm;
-    tm.pos64 = pos_buf;
-    tm.pos32 = reinterpret_cast<float4*>(pos_buf);
+    const int team = G > 1 ? (int)threadIdx.x / LG : 0;
+    Team<W, A, POT, L, G> tm;
+    tm.li = G > 1 ? (int)threadIdx.x % LG : (int)threadIdx.x;
+    tm.pos64 = pos_buf + team * LG;
+    tm.pos32 = reinterpret_cast<float4*>(pos_buf) + team * LG;
     tm.rbuf = tile_rbuf;
     tm.sc = &scratch;
     tm.bank = 0;
@@ -614,22 +667,24 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
     const int count = args.plan.cls[kNumClasses + args.cls];
     const int64_t total = args.total;
     for (;;) {
-        if (threadIdx.x == 0) claim = atomicAdd(&args.plan.queue[args.cls], 1);
+        if (threadIdx.x == 0) claim = atomicAdd(&args.plan.queue[args.cls], G);
         __syncthreads();
-        const int idx = claim;
+        const int idx0 = claim;
         __syncthreads();
-        if (idx >= count) break;
-        const int b = args.plan.list[start + idx];
-        const int o = args.offset[b];
-        const int n = args.offset[b + 1] - o;
-        tm.n = n;  // the plan guarantees 0 <= n <= T*A
+        if (idx0 >= count) break;
+        const int idx = idx0 + team;
+        const bool has = idx < count;  // a packed team past the end idles
+        const int b = has ? args.plan.list[start + idx] : 0;
+        const int o = has ? args.offset[b] : 0;
+        const int n = has ? args.offset[b + 1] - o : 0;
+        tm.n = n;  // the plan guarantees 0 <= n <= T*A (G > 1: <= 64 / G)
 
         double x[3][A], g[3][A];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int a = 0; a < A; ++a) {
-                const int i = a * T + threadIdx.x;
+                const int i = a * T + tm.li;
                 x[c][a] = i < n ? args.xyz[c * total + o + i] : 0.0;
             }
         double E = 0.0, gn = 0.0;
@@ -651,7 +706,7 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int a = 0; a < A; ++a) {
-                        const int i = a * T + threadIdx.x;
+                        const int i = a * T + tm.li;
                         if (i < n) args.xyz_switch[c * total + o + i] = x[c][a];
                     }
             }
@@ -676,10 +731,10 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int a = 0; a < A; ++a) {
-                const int i = a * T + threadIdx.x;
+                const int i = a * T + tm.li;
                 if (i < n) args.xyz[c * total + o + i] = x[c][a];
             }
-        if (threadIdx.x == 0) {
+        if (has && tm.li == 0) {
             args.energy[b] = E;
             args.gnorm[b] = gn;
             args.iters[b] = iters;
@@ -770,6 +825,7 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
     tm.sc = &scratch;
     tm.bank = 0;
     tm.n = n;
+    tm.li = threadIdx.x;
     tm.rho = rho;
     double x[3][A], g[3][A];
 #pragma unroll
@@ -852,27 +908,33 @@ hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const in
                  : launch_eval_t<0, kPairLJ>(s, num, off, total, xyz, e, g, rho, st);
 }
 
-// Minimiser shapes.  Classes 0-2 keep the history in registers (one, two,
-// four wavefronts, one atom per lane).  Class 3 (N in 257..1024) keeps it in a
-// global ring and has three interchangeable shapes of 1024 atom slots:
-// 16 wavefronts x 1 atom, 8 x 2, 4 x 4 (chosen by the schedule table).
-// "narrow": every cluster of the class lies in the lower part of its range,
-// so a leaner kernel serves it: class 0 with at most 16 atoms reduces over
-// one 16-lane row, class 2 with at most 192 atoms (three 64-atom tiles) runs
-// three wavefronts instead of four, leaving a SIMD free for other work.
+// Minimiser shapes.  Classes 0-2 keep the history in registers; class 3
+// (N in 257..1024) keeps it in a global ring.  Each class has interchangeable
+// shapes (the schedule table or the built-in rule picks one per call):
+//   class 0 (N <= 64):   0  one wavefront per cluster
+//                        1  one wavefront, reductions over one 16-lane row
+//                           (N <= 16)
+//                        2  two clusters per wavefront, 32 lanes each (N <= 32)
+//                        3  four clusters per wavefront, 16 lanes each (N <= 16)
+//   class 1 (N <= 128):  0  two wavefronts;  1  one wavefront, two atoms per lane
+//   class 2 (N <= 256):  0  four wavefronts;  1  three wavefronts (N <= 192)
+//   class 3 (N <= 1024): 0  16 wavefronts x 1 atom, 1  8 x 2, 2  4 x 4
 struct ClassShape {
     int W, A;
     bool hreg;
+    int G;     // clusters per workgroup
+    int max_n; // largest cluster the shape holds
 };
-constexpr ClassShape kClassShape[kNumClasses] = {{1, 1, true}, {2, 1, true}, {4, 1, true},
-                                                 {16, 1, false}};
-constexpr ClassShape kLargeShape[kNumLargeShapes] = {{16, 1, false}, {8, 2, false}, {4, 4, false}};
+constexpr int kShapes[kNumClasses] = {4, 2, 2, 3};
+constexpr ClassShape kShape[kNumClasses][4] = {
+    {{1, 1, true, 1, 64}, {1, 1, true, 1, 16}, {1, 1, true, 2, 32}, {1, 1, true, 4, 16}},
+    {{2, 1, true, 1, 128}, {1, 2, true, 1, 128}, {}, {}},
+    {{4, 1, true, 1, 256}, {3, 1, true, 1, 192}, {}, {}},
+    {{16, 1, false, 1, 1024}, {8, 2, false, 1, 1024}, {4, 4, false, 1, 1024}, {}}};
 
-static ClassShape shape_of(int c, int large, bool narrow) {
-    if (c == 1 && narrow) return {1, 2, true};
-    if (c == 2 && narrow) return {3, 1, true};
-    return c == 3 ? kLargeShape[large] : kClassShape[c];
-}
+int class_shapes(int c) { return c >= 0 && c < kNumClasses ? kShapes[c] : 0; }
+int shape_max_n(int c, int shape) { return kShape[c][shape].max_n; }
+int shape_clusters_per_wg(int c, int shape) { return kShape[c][shape].G; }
 
 int class_of(int n) {
     for (int c = 0; c < kNumClasses; ++c)
@@ -880,53 +942,43 @@ int class_of(int n) {
     return -1;
 }
 
-size_t class_hist_bytes_per_wg(int c, int large) {
-    const ClassShape s = shape_of(c, large, false);
+size_t class_hist_bytes_per_wg(int c, int shape) {
+    const ClassShape s = kShape[c][shape];
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
-template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave>
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1>
 static const void* min_kernel_ptr() {
-    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT, L>);
+    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT, L, G>);
 }
 
-template <int POT>
-static const void* minimize_kernel_pot(int mixed, int c, int large, bool narrow) {
-    if (c == 0 && narrow)  // every cluster of the class has at most 16 atoms
-        return mixed ? min_kernel_ptr<1, 1, 1, true, POT, 16>()
-                     : min_kernel_ptr<0, 1, 1, true, POT, 16>();
-    if (c == 1 && narrow)  // one wavefront, two atoms per lane (see min_layout)
-        return mixed ? min_kernel_ptr<1, 1, 2, true, POT>() : min_kernel_ptr<0, 1, 2, true, POT>();
-    if (c == 2 && narrow)  // every cluster of the class has at most 192 atoms
-        return mixed ? min_kernel_ptr<1, 3, 1, true, POT>() : min_kernel_ptr<0, 3, 1, true, POT>();
-    if (c < 3) {
-        switch (c * 2 + (mixed ? 1 : 0)) {
-            case 0: return min_kernel_ptr<0, 1, 1, true, POT>();
-            case 1: return min_kernel_ptr<1, 1, 1, true, POT>();
-            case 2: return min_kernel_ptr<0, 2, 1, true, POT>();
-            case 3: return min_kernel_ptr<1, 2, 1, true, POT>();
-            case 4: return min_kernel_ptr<0, 4, 1, true, POT>();
-            case 5: return min_kernel_ptr<1, 4, 1, true, POT>();
-        }
-        return nullptr;
-    }
-    switch (large * 2 + (mixed ? 1 : 0)) {
-        case 0: return min_kernel_ptr<0, 16, 1, false, POT>();
-        case 1: return min_kernel_ptr<1, 16, 1, false, POT>();
-        case 2: return min_kernel_ptr<0, 8, 2, false, POT>();
-        case 3: return min_kernel_ptr<1, 8, 2, false, POT>();
-        case 4: return min_kernel_ptr<0, 4, 4, false, POT>();
-        case 5: return min_kernel_ptr<1, 4, 4, false, POT>();
+template <int MIXED, int POT>
+static const void* minimize_kernel_pm(int c, int shape) {
+    switch (c * 4 + shape) {
+        case 0: return min_kernel_ptr<MIXED, 1, 1, true, POT>();
+        case 1: return min_kernel_ptr<MIXED, 1, 1, true, POT, 16>();
+        case 2: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 2>();
+        case 3: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 4>();
+        case 4: return min_kernel_ptr<MIXED, 2, 1, true, POT>();
+        case 5: return min_kernel_ptr<MIXED, 1, 2, true, POT>();
+        case 8: return min_kernel_ptr<MIXED, 4, 1, true, POT>();
+        case 9: return min_kernel_ptr<MIXED, 3, 1, true, POT>();
+        case 12: return min_kernel_ptr<MIXED, 16, 1, false, POT>();
+        case 13: return min_kernel_ptr<MIXED, 8, 2, false, POT>();
+        case 14: return min_kernel_ptr<MIXED, 4, 4, false, POT>();
     }
     return nullptr;
 }
 
-const void* minimize_kernel_for(int mixed, int pot, int c, int large, bool narrow) {
-    return pot == kPairMorse ? minimize_kernel_pot<kPairMorse>(mixed, c, large, narrow)
-                             : minimize_kernel_pot<kPairLJ>(mixed, c, large, narrow);
+const void* minimize_kernel_for(int mixed, int pot, int c, int shape) {
+    if (c < 0 || c >= kNumClasses || shape < 0 || shape >= kShapes[c]) return nullptr;
+    if (pot == kPairMorse)
+        return mixed ? minimize_kernel_pm<1, kPairMorse>(c, shape)
+                     : minimize_kernel_pm<0, kPairMorse>(c, shape);
+    return mixed ? minimize_kernel_pm<1, kPairLJ>(c, shape) : minimize_kernel_pm<0, kPairLJ>(c, shape);
 }
 
-int class_block(int c, int large, bool narrow) { return kWave * shape_of(c, large, narrow).W; }
+int class_block(int c, int shape) { return kWave * kShape[c][shape].W; }
 
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st) {
@@ -935,12 +987,12 @@ hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_minimize_class(int mixed, int c, int large, bool narrow, int grid,
-                                 const MinArgs& a, hipStream_t st) {
-    const void* k = minimize_kernel_for(mixed, a.pot, c, large, narrow);
+hipError_t launch_minimize_class(int mixed, int c, int shape, int grid, const MinArgs& a,
+                                 hipStream_t st) {
+    const void* k = minimize_kernel_for(mixed, a.pot, c, shape);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {const_cast<MinArgs*>(&a)};
-    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, large, narrow)), args, 0, st);
+    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, shape)), args, 0, st);
 }
 
 }  // namespace lj

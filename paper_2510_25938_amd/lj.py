@@ -19,6 +19,10 @@ CONVERGED, MAXITER, LSFAIL, NONFINITE, SWITCHED, BADSIZE = 0, 1, 2, 3, 4, 5
 OK, E_ARG, E_HIP, E_WORKSPACE, E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_ATOMS_EVAL, MAX_ATOMS_MIN, MAX_M, MAX_CANDS = 4096, 1024, 10, 64
 SCHED_EVAL, SCHED_MIN_LARGE = 0, 1
+SCHED_MIN_CLASS = (2, 3, 4)  # minimiser shape of size classes 0, 1, 2
+# shapes per class: (clusters per workgroup, largest N) for each shape index
+CLASS_SHAPES = {0: ((1, 64), (1, 16), (2, 32), (4, 16)), 1: ((1, 128), (1, 128)),
+                2: ((1, 256), (1, 192))}
 EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
             "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_set_schedule",
             "lj_get_schedule", "lj_autotune_workspace_bytes", "lj_autotune", "lj_status_string",
@@ -312,7 +316,9 @@ def autotune(batch, xyz, precision="mixed", stream=None, cache=None):
 
     Synchronises the stream.  With `cache` (a JSON path) the chosen schedules
     are merged into that file; `load_schedules` installs them in a new process.
-    Returns {"eval": (W, A, ms), "min_large": (shape, ms) or None}.
+    Returns {"eval": (W, A, ms), "min_large": shape or None, "min_ms": ms of a
+    minimisation with the chosen shapes or None, "min_class": {class: shape}
+    for the size classes the batch holds}.
     """
     prec = precision_code(precision)
     nb = int(lib().lj_autotune_workspace_bytes(C.byref(batch.desc()), prec))
@@ -324,9 +330,16 @@ def autotune(batch, xyz, precision="mixed", stream=None, cache=None):
     _check(lib().lj_autotune(C.byref(batch.desc()), _ptr(xyz), prec, _ptr(ws), nb,
                              _stream(stream), C.byref(t_eval), C.byref(t_min)))
     w, a = get_schedule(SCHED_EVAL, prec, batch.max_n)
-    res = {"eval": (w, a, t_eval.value), "min_large": None}
+    res = {"eval": (w, a, t_eval.value), "min_large": None, "min_ms": None, "min_class": {}}
     if t_min.value >= 0:
-        res["min_large"] = (get_schedule(SCHED_MIN_LARGE, prec)[0], t_min.value)
+        res["min_ms"] = t_min.value
+        if batch.max_n > 256:
+            res["min_large"] = get_schedule(SCHED_MIN_LARGE, prec)[0]
+        for c in range(3):
+            if c <= _class_of(batch.max_n):
+                k = get_schedule(SCHED_MIN_CLASS[c], prec, batch.max_n)[0]
+                if k >= 0:
+                    res["min_class"][c] = k
     if cache:
         import json
         table = {}
@@ -339,7 +352,10 @@ def autotune(batch, xyz, precision="mixed", stream=None, cache=None):
             p2 *= 2
         table.setdefault(key, {}).setdefault("eval", {})[str(p2)] = [w, a]
         if res["min_large"] is not None:
-            table[key]["min_large"] = res["min_large"][0]
+            table[key]["min_large"] = res["min_large"]
+        if res["min_class"]:
+            table[key].setdefault("min_class", {})[str(batch.max_n)] = {
+                str(c): k for c, k in res["min_class"].items()}
         with open(cache, "w") as fh:
             json.dump(table, fh, indent=1, sort_keys=True)
     return res
@@ -356,6 +372,16 @@ def load_schedules(cache):
             set_schedule(SCHED_EVAL, prec, int(p2), w, a)
         if "min_large" in entry:
             set_schedule(SCHED_MIN_LARGE, prec, 0, entry["min_large"], 0)
+        for max_n, shapes in entry.get("min_class", {}).items():
+            for c, k in shapes.items():
+                set_schedule(SCHED_MIN_CLASS[int(c)], prec, int(max_n), k, 0)
+
+
+def _class_of(n):
+    for c, lim in enumerate((64, 128, 256, MAX_ATOMS_MIN)):
+        if n <= lim:
+            return c
+    return -1
 
 
 def bh_params(cands=8, kT=0.8, adapt_interval=10, target_rate=0.5, factor=0.9, seed=0):
