@@ -259,7 +259,7 @@ def errors_at_results(O, off, h, pair="lj", rho=6.0):
             "gnorm_oracle_at_result_median": float(np.median(gn))}
 
 
-WORKLOADS = ("lj13bh", "uneven", "large", "morse", "chains")
+WORKLOADS = ("lj13bh", "uneven", "large", "morse", "chains", "small")
 
 
 def workloads(lj, inputs, torch, stream, oracle=None, only=None):
@@ -276,7 +276,55 @@ def workloads(lj, inputs, torch, stream, oracle=None, only=None):
         res.update(morse_batch(lj, inputs, torch, stream, oracle))
     if only in (None, "chains"):
         res.update(many_chains(lj, inputs, torch, stream, oracle))
+    if only in (None, "small"):
+        res.update(small_batch(lj, inputs, torch, stream, oracle))
     return res
+
+
+def reset_class_schedules(lj, max_n):
+    for prec in ("fp64", "mixed"):
+        for c in range(3):
+            if c <= lj._class_of(max_n):
+                lj.set_schedule(lj.SCHED_MIN_CLASS[c], prec, max_n, -1)
+
+
+def small_batch(lj, inputs, torch, stream, O):
+    """16384 LJ13 clusters, FP64 and mixed, in one call: the built-in
+    schedule (four clusters per wavefront at this batch size) against one
+    cluster per wavefront reduced over a 16-lane row, the fastest one-cluster
+    shape.  The oracle on the first 512 clusters checks the FP64 results."""
+    dev = "cuda"
+    w = inputs.lj13_batch()
+    off, x = w.starts()
+    b = lj.ClusterBatch(off, device=dev)
+    xd = torch.from_numpy(x).to(dev)
+    pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
+    entry, host = minimize_legs(lj, b, xd, lj.lbfgs_params(), torch, stream, pairs)
+    entry["shape"] = "four clusters per wavefront"
+    one = {}
+    for prec in ("fp64", "mixed"):
+        lj.set_schedule(lj.SCHED_MIN_CLASS[0], prec, b.max_n, 1)
+        ms, _ = timed(torch, stream, lambda _: lj.minimize(b, xd, lj.lbfgs_params(), prec,
+                                                           stream=stream))
+        one[prec] = {"ms": ms, "minimisations_per_s": b.num / (ms * 1e-3)}
+    reset_class_schedules(lj, b.max_n)
+    entry["one_cluster_per_wavefront"] = one
+    entry["speedup_packed_vs_one_per_wavefront"] = {
+        p: one[p]["ms"] / entry[p]["ms"] for p in ("fp64", "mixed")}
+    if O is not None:
+        sub = 512
+        t0 = time.perf_counter()
+        ro = O.minimize(off[:sub + 1], x[:, :off[sub]])
+        sec = time.perf_counter() - t0
+        h = {k: (v[:, :off[sub]] if k == "xyz" else v[:sub]) for k, v in host["fp64"].items()}
+        entry["cpu_oracle"] = {"minimisations_per_s": sub / sec, "cores": 1,
+                               "sample": f"the first {sub} clusters, FP64, one thread "
+                                         f"({sec:.2f} s)"}
+        entry["parity"] = {"fp64_bitwise_frac_subset": per_cluster_equal(h, ro, off[:sub + 1]),
+                           "fp64_subset": sub,
+                           **{"mixed_" + k: v for k, v in
+                              errors_at_results(O, off, host["mixed"]).items()}}
+    return {w.name: entry}
 
 
 def lj13_chain(lj, inputs, torch, stream, oracle):
@@ -301,6 +349,19 @@ def lj13_chain(lj, inputs, torch, stream, oracle):
     e_best = float(c.e_best_acc[0].item())
     entry = {"chain_steps_per_s": w.steps / (ms * 1e-3), "ms": ms, "reps": 5, "stat": "median",
              "best_energy": e_best, "reached_lj13_minimum": abs(e_best + 44.326801) < 1e-6}
+    # the autotuner on the step's candidate batch (8 perturbed copies of the
+    # start minimum), then the chain again with the tuned shapes
+    cand_off = np.arange(w.cands + 1, dtype=np.int32) * 13
+    cb = lj.ClusterBatch(cand_off, device=dev)
+    xc8 = r0["xyz"].repeat(1, w.cands).contiguous()
+    xc8 = xc8 + 0.4 * (2 * torch.rand(xc8.shape, generator=torch.Generator(device=dev)
+                                      .manual_seed(w.seed), device=dev, dtype=torch.float64) - 1)
+    tune = lj.autotune(cb, xc8, "fp64", stream=stream)
+    ms_t, c_t = timed(torch, stream, chain, setup=setup)
+    entry["tuned"] = {"chain_steps_per_s": w.steps / (ms_t * 1e-3), "ms": ms_t,
+                      "class0_shape": tune["min_class"].get(0),
+                      "same_chain": bool(torch.equal(c_t.xyz_cur, c.xyz_cur))}
+    reset_class_schedules(lj, 13)
     if oracle is not None:
         xc = r0["xyz"].cpu().numpy().copy()
         st = [oracle.chain_state(float(r0["energy"][0].item()), w.step0)]
@@ -347,6 +408,20 @@ def uneven_batch(lj, inputs, torch, stream, O):
     params = lj.lbfgs_params()
     pairs = (b.sizes * (b.sizes - 1) // 2).astype(np.int64)
     entry, host = minimize_legs(lj, b, xd, params, torch, stream, pairs)
+    tuned = {}
+    for prec in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        res = lj.autotune(b, xd, prec, stream=stream)
+        tune_s = time.perf_counter() - t0
+        ms, r = timed(torch, stream, lambda _: lj.minimize(b, xd, params, prec, stream=stream))
+        tuned[prec] = {"ms": ms, "default_ms": entry[prec]["ms"], "shapes": res["min_class"],
+                       "autotune_s": tune_s,
+                       "same_results": bool(torch.equal(r["energy"].cpu(),
+                                                        torch.from_numpy(host[prec]["energy"])))}
+    reset_class_schedules(lj, b.max_n)
+    lj.set_schedule(lj.SCHED_EVAL, "mixed", b.max_n, *lj.eval_shape_default(b.max_n))
+    lj.set_schedule(lj.SCHED_EVAL, "fp64", b.max_n, *lj.eval_shape_default(b.max_n))
+    entry["tuned"] = tuned
     if O is None:
         return {w.name: entry}
     ro, sec, P = oracle_minimize_pool(O, off, x)

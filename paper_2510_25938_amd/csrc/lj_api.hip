@@ -158,7 +158,17 @@ std::array<int, 4> class_key(int precision, int c, int max_n) {
 // Built-in rule for the shape of class c (0-2).
 int default_class_shape(int c, int max_n, int top_class, int mixed, int num, int cus) {
     const int cmax = class_cap(c, max_n);
-    if (c == 0) return cmax <= 16 ? 1 : 0;  // one 16-lane row
+    if (c == 0) {
+        // Several clusters per wavefront once the batch has more than two
+        // clusters per SIMD: each wavefront then does the work of two or four
+        // (16384 x LJ13: 1.75 instead of 4.2 ms, FP64); below that the batch
+        // waits for its slowest cluster, and a packed wavefront waits for the
+        // slowest of its clusters, so one cluster per wavefront is as fast.
+        const bool many = num > 2 * 4 * cus;
+        if (cmax <= 16) return many ? 3 : 1;
+        if (cmax <= 32 && many) return 2;
+        return 0;
+    }
     if (c == 2) return cmax <= 192 ? 1 : 0; // three wavefronts
     // Class 1 as one wavefront with two atoms per lane: about 1.5 times the
     // time per iteration of two wavefronts, but one SIMD per team instead of

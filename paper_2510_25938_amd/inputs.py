@@ -117,3 +117,10 @@ def morse38_batch(count: int = 1024, rho: float = 6.0) -> Workload:
     starts, one launch: the LJ38 batch with the Morse pair."""
     return Workload(f"morse38-rho{rho:g}-batch-{count}", np.full(count, 38), SEED_BASE + 6,
                     "mixed", extra={"pair": "morse", "rho": rho})
+
+
+def lj13_batch(count: int = 16384) -> Workload:
+    """16384 independent LJ13 candidates from random cube starts, one launch:
+    the small-cluster end of the batched minimiser (the paper's LJ13 candidate
+    shape at many chains' worth of candidates)."""
+    return Workload(f"lj13-batch-{count}", np.full(count, 13), SEED_BASE + 7, "fp64")
