@@ -85,16 +85,22 @@ typedef int32_t lj_status;
  * empirical pair force field of the kind the paper's conclusions name as the
  * next potentials, in reduced units with well depth 1 at r = 1:
  *   V(r) = t (t - 2),  t = exp(rho (1 - r)),  rho = lj_batch.pair_rho > 0
- * (rho = 6 has the curvature of Eq. (1) at its minimum).  Other sigma and
- * epsilon (or well depth and position) are host rescalings: E(x) =
- * epsilon E_reduced(x / sigma), g = (epsilon / sigma) g_reduced. */
+ * (rho = 6 has the curvature of Eq. (1) at its minimum).
+ * Units (lj_batch.sigma, lj_batch.epsilon; 0 means 1): the coordinates the
+ * caller passes and receives are in units of sigma (the well position), the
+ * energies in units of epsilon (the well depth).  The kernels divide each
+ * loaded coordinate by sigma (one IEEE division) and work in reduced units;
+ * they report E = epsilon E_reduced, g = (epsilon / sigma) g_reduced,
+ * ||g|| likewise, and coordinates times sigma.  The minimiser's parameters
+ * (gtol, max_step, ...) stay in reduced units.  Basin hopping takes reduced
+ * units only. */
 #define LJ_PAIR_LJ 0
 #define LJ_PAIR_MORSE 1
 
 /* A ragged batch.  offset is a device pointer; the other fields are host
  * values that must agree with it: num = B >= 0, max_n >= every N_b,
- * total_atoms = offset[B].  pair and pair_rho select the pair potential
- * (zero-initialised: Eq. (1)). */
+ * total_atoms = offset[B].  pair and pair_rho select the pair potential,
+ * sigma and epsilon the units (zero-initialised: Eq. (1), reduced units). */
 typedef struct {
     int32_t num;
     const int32_t* offset;
@@ -102,6 +108,8 @@ typedef struct {
     int64_t total_atoms;
     int32_t pair;    /* LJ_PAIR_LJ or LJ_PAIR_MORSE                       */
     double pair_rho; /* Morse range rho (finite, > 0); ignored for Eq. (1) */
+    double sigma;    /* length unit (finite, > 0; 0 means 1)              */
+    double epsilon;  /* energy unit (finite, > 0; 0 means 1)              */
 } lj_batch;
 
 /*
@@ -345,7 +353,7 @@ const char* lj_status_string(lj_status s);
 const char* lj_last_error(void);
 
 /* ABI version of this header (incremented on any incompatible change). */
-#define LJ_ABI_VERSION 3
+#define LJ_ABI_VERSION 4
 int32_t lj_abi_version(void);
 
 /* Number of basin-hopping step graphs captured by this process so far (a

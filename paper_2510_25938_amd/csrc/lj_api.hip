@@ -80,7 +80,23 @@ lj_status check_batch(const lj_batch* b, int limit, const char* what) {
                     b->pair);
     if (b->pair == LJ_PAIR_MORSE && !(b->pair_rho > 0.0 && b->pair_rho <= 1.0e6))
         return fail(LJ_E_ARG, "%s: Morse pair_rho = %g is not in (0, 1e6]", what, b->pair_rho);
+    if (!(b->sigma == 0.0 || (b->sigma > 0.0 && std::isfinite(b->sigma))) ||
+        !(b->epsilon == 0.0 || (b->epsilon > 0.0 && std::isfinite(b->epsilon))))
+        return fail(LJ_E_ARG, "%s: sigma = %g and epsilon = %g must be finite and > 0 (or 0 for 1)",
+                    what, b->sigma, b->epsilon);
     return LJ_OK;
+}
+
+// The batch's units; a zero sigma or epsilon means 1.
+lj::Units units_of(const lj_batch* b) {
+    const double sg = b->sigma == 0.0 ? 1.0 : b->sigma;
+    const double ep = b->epsilon == 0.0 ? 1.0 : b->epsilon;
+    return lj::Units{sg, ep, ep / sg, sg != 1.0};
+}
+
+bool reduced_units(const lj_batch* b) {
+    const lj::Units u = units_of(b);
+    return u.sigma == 1.0 && u.escale == 1.0;
 }
 
 lj_status check_params(const lj_lbfgs_params* p) {
@@ -323,6 +339,7 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     a.p = p;
     a.pot = b->pair;
     a.rho = b->pair_rho;
+    a.u = units_of(b);
     if (L.top_class == 0) {
         a.cls = 0;
         a.hist = nullptr;
@@ -412,6 +429,9 @@ lj_status bh_layout(const lj_batch* ch, const lj_bh_params* bh, int mixed, BhLay
 
 lj_status check_bh(const lj_batch* ch, const lj_bh_params* bh) {
     if (!bh) return fail(LJ_E_ARG, "bh params is NULL");
+    if (!reduced_units(ch))
+        return fail(LJ_E_UNSUPPORTED, "basin hopping runs in reduced units: sigma and epsilon "
+                    "of the chains' batch must be 1 (or 0)");
     if (bh->cands < 1 || bh->cands > LJ_MAX_CANDS)
         return fail(LJ_E_ARG, "cands = %d outside [1, %d]", bh->cands, LJ_MAX_CANDS);
     if (!(bh->kT > 0.0)) return fail(LJ_E_ARG, "kT must be > 0");
@@ -439,6 +459,8 @@ lj_status enqueue_bh_step(const lj_batch* ch, const lj::BhStateDev& s, const lj:
     cb.total_atoms = L.cand_total;
     cb.pair = ch->pair;
     cb.pair_rho = ch->pair_rho;
+    cb.sigma = 1.0;
+    cb.epsilon = 1.0;
     lj::LbfgsDev d = to_dev(lp);
     if (mixed) d.polish = 0;  // only the accepted candidate is polished
     lj_status r = enqueue_minimize(&cb, nullptr, xc, ce, reinterpret_cast<double*>(ws + L.cg),
@@ -502,6 +524,8 @@ std::vector<unsigned char> step_key(const lj_batch* ch, const lj::BhStateDev& sd
     key_add(k, ch->total_atoms);
     key_add(k, ch->pair);
     key_add(k, ch->pair_rho);
+    key_add(k, ch->sigma);
+    key_add(k, ch->epsilon);
     for (const void* ptr : {(const void*)sd.xyz_cur, (const void*)sd.e_cur, (const void*)sd.step,
                             (const void*)sd.win_accepts, (const void*)sd.step_index,
                             (const void*)sd.e_best_seen, (const void*)sd.e_best_acc,
@@ -622,7 +646,8 @@ lj_status lj_energy_grad_batch(const lj_batch* batch, const double* xyz, double*
     LJ_HIP_TRY(lj::launch_energy_grad(precision == LJ_MIXED, batch->pair,
                                       eval_schedule(precision, batch->max_n), batch->num,
                                       batch->offset, batch->total_atoms, xyz, energy, grad,
-                                      batch->pair_rho, static_cast<hipStream_t>(stream)));
+                                      batch->pair_rho, units_of(batch),
+                                      static_cast<hipStream_t>(stream)));
     return LJ_OK;
 }
 
@@ -943,7 +968,7 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
             s = time_it([&]() -> lj_status {
                 LJ_HIP_TRY(lj::launch_energy_grad(mixed, batch->pair, sh, batch->num,
                                                   batch->offset, batch->total_atoms, xyz, e, g,
-                                                  batch->pair_rho, st));
+                                                  batch->pair_rho, units_of(batch), st));
                 return LJ_OK;
             }, ms);
             if (s != LJ_OK) break;

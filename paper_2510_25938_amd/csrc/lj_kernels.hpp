@@ -34,6 +34,16 @@ struct Plan {
     int32_t* queue;     // claim counters [kNumClasses]
 };
 
+// Units of the caller's coordinates and energies (lj_batch.sigma, .epsilon):
+// the kernels work in reduced units, x_reduced = x / sigma, and report
+// E = epsilon E_reduced and g = (epsilon / sigma) g_reduced.
+struct Units {
+    double sigma;
+    double escale;  // epsilon
+    double gscale;  // epsilon / sigma
+    int scaled;     // sigma != 1
+};
+
 struct MinArgs {
     const int32_t* offset;
     int64_t total;
@@ -50,6 +60,7 @@ struct MinArgs {
     LbfgsDev p;
     int pot;            // LJ_PAIR_LJ or LJ_PAIR_MORSE
     double rho;         // Morse range
+    Units u;
 };
 
 // Launchers (lj_minimize.hip, lj_bh_kernels.hip).
@@ -61,7 +72,7 @@ EvalShape eval_shape(int max_n);
 bool eval_shape_supported(EvalShape s);
 hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const int32_t* off,
                               int64_t total, const double* xyz, double* e, double* g, double rho,
-                              hipStream_t st);
+                              Units u, hipStream_t st);
 // Minimiser shapes per size class (see lj_minimize.hip): class_shapes(c)
 // interchangeable kernels; shape s holds clusters of at most
 // shape_max_n(c, s) atoms, shape_clusters_per_wg(c, s) of them per workgroup.

@@ -686,6 +686,7 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
             for (int a = 0; a < A; ++a) {
                 const int i = a * T + tm.li;
                 x[c][a] = i < n ? args.xyz[c * total + o + i] : 0.0;
+                if (args.u.scaled) x[c][a] = x[c][a] / args.u.sigma;
             }
         double E = 0.0, gn = 0.0;
         int iters = 0, evals = 0, st = LJ_CONVERGED;
@@ -707,7 +708,9 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
 #pragma unroll
                     for (int a = 0; a < A; ++a) {
                         const int i = a * T + tm.li;
-                        if (i < n) args.xyz_switch[c * total + o + i] = x[c][a];
+                        if (i < n)
+                            args.xyz_switch[c * total + o + i] =
+                                args.u.scaled ? x[c][a] * args.u.sigma : x[c][a];
                     }
             }
             if (!args.p.polish) {
@@ -732,11 +735,12 @@ __global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
 #pragma unroll
             for (int a = 0; a < A; ++a) {
                 const int i = a * T + tm.li;
-                if (i < n) args.xyz[c * total + o + i] = x[c][a];
+                if (i < n)
+                    args.xyz[c * total + o + i] = args.u.scaled ? x[c][a] * args.u.sigma : x[c][a];
             }
         if (has && tm.li == 0) {
-            args.energy[b] = E;
-            args.gnorm[b] = gn;
+            args.energy[b] = E * args.u.escale;
+            args.gnorm[b] = gn * args.u.gscale;
             args.iters[b] = iters;
             args.evals[b] = evals;
             args.status[b] = st;
@@ -804,7 +808,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(const int32_t* offset, int n
 template <int MIXED, int W, int A, int POT>
 __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* offset, int64_t total,
                                                                const double* xyz, double* energy,
-                                                               double* grad, double rho) {
+                                                               double* grad, double rho, Units u) {
     constexpr int T = kWave * W;
     __shared__ double4 pos_buf[T * A];
     __shared__ TeamScratch<W, 4 * A> scratch;
@@ -834,16 +838,17 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
         for (int a = 0; a < A; ++a) {
             const int i = a * T + threadIdx.x;
             x[c][a] = i < n ? xyz[c * total + o + i] : 0.0;
+            if (u.scaled) x[c][a] = x[c][a] / u.sigma;
         }
     const double E = tm.template eval<MIXED != 0>(x, g);
-    if (threadIdx.x == 0) energy[b] = E;
+    if (threadIdx.x == 0) energy[b] = E * u.escale;
     if (grad) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int a = 0; a < A; ++a) {
                 const int i = a * T + threadIdx.x;
-                if (i < n) grad[c * total + o + i] = g[c][a];
+                if (i < n) grad[c * total + o + i] = g[c][a] * u.gscale;
             }
     }
 }
@@ -870,13 +875,13 @@ bool eval_shape_supported(EvalShape s) {
 
 template <int MIXED, int POT>
 static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_t total,
-                                const double* xyz, double* e, double* g, double rho,
+                                const double* xyz, double* e, double* g, double rho, Units u,
                                 hipStream_t st) {
     dim3 grid(num), block(kWave * s.W);
 #define LJ_EVAL_CASE(WW, AA)                                                                  \
     if (s.W == WW && s.A == AA) {                                                             \
         hipLaunchKernelGGL((energy_grad_kernel<MIXED, WW, AA, POT>), grid, block, 0, st, off, \
-                           total, xyz, e, g, rho);                                            \
+                           total, xyz, e, g, rho, u);                                         \
         return hipGetLastError();                                                             \
     }
     LJ_EVAL_CASE(1, 1)
@@ -900,12 +905,12 @@ static hipError_t launch_eval_t(EvalShape s, int num, const int32_t* off, int64_
 
 hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const int32_t* off,
                               int64_t total, const double* xyz, double* e, double* g, double rho,
-                              hipStream_t st) {
+                              Units u, hipStream_t st) {
     if (pot == kPairMorse)
-        return mixed ? launch_eval_t<1, kPairMorse>(s, num, off, total, xyz, e, g, rho, st)
-                     : launch_eval_t<0, kPairMorse>(s, num, off, total, xyz, e, g, rho, st);
-    return mixed ? launch_eval_t<1, kPairLJ>(s, num, off, total, xyz, e, g, rho, st)
-                 : launch_eval_t<0, kPairLJ>(s, num, off, total, xyz, e, g, rho, st);
+        return mixed ? launch_eval_t<1, kPairMorse>(s, num, off, total, xyz, e, g, rho, u, st)
+                     : launch_eval_t<0, kPairMorse>(s, num, off, total, xyz, e, g, rho, u, st);
+    return mixed ? launch_eval_t<1, kPairLJ>(s, num, off, total, xyz, e, g, rho, u, st)
+                 : launch_eval_t<0, kPairLJ>(s, num, off, total, xyz, e, g, rho, u, st);
 }
 
 // Minimiser shapes.  Classes 0-2 keep the history in registers; class 3

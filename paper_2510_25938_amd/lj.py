@@ -36,7 +36,8 @@ PAIRS = {"lj": 0, "morse": 1}  # LJ_PAIR_LJ (Eq. 1), LJ_PAIR_MORSE
 
 class Batch(C.Structure):
     _fields_ = [("num", C.c_int32), ("offset", C.c_void_p), ("max_n", C.c_int32),
-                ("total_atoms", C.c_int64), ("pair", C.c_int32), ("pair_rho", C.c_double)]
+                ("total_atoms", C.c_int64), ("pair", C.c_int32), ("pair_rho", C.c_double),
+                ("sigma", C.c_double), ("epsilon", C.c_double)]
 
 
 class LbfgsParams(C.Structure):
@@ -184,38 +185,25 @@ class ClusterBatch:
         self.offset_host = off.astype(np.int32)
         self.offset = torch.from_numpy(self.offset_host).to(device)
 
-    def desc(self, max_n=None):
+    def desc(self, max_n=None, sigma=1.0, epsilon=1.0):
+        """The C descriptor; sigma / epsilon: the units of the coordinates and
+        energies passed in and out (the library converts; kernels work in
+        reduced units)."""
         return Batch(self.num, self.offset.data_ptr(), self.max_n if max_n is None else max_n,
-                     self.total, PAIRS[self.pair], self.rho)
-
-
-# Units.  The kernels work in reduced units (sigma = epsilon = 1 for Eq. (1);
-# well position and depth 1 for the Morse pair).  Other length and energy
-# units are a conversion of the inputs and outputs: E(x) = epsilon
-# E_reduced(x / sigma), g(x) = (epsilon / sigma) g_reduced(x / sigma).
-def to_reduced(xyz, sigma=1.0):
-    return xyz if sigma == 1.0 else (xyz / sigma).contiguous()
-
-
-def from_reduced(energy=None, grad=None, xyz=None, sigma=1.0, epsilon=1.0):
-    return (None if energy is None else energy * epsilon,
-            None if grad is None else grad * (epsilon / sigma),
-            None if xyz is None else xyz * sigma)
+                     self.total, PAIRS[self.pair], self.rho, float(sigma), float(epsilon))
 
 
 def energy_grad(batch, xyz, precision="fp64", grad=True, stream=None, sigma=1.0, epsilon=1.0):
     """Energies [num] and gradient planes [3][total] (None if grad=False) of the
-    batch's pair potential; sigma / epsilon convert from other units."""
+    batch's pair potential, for coordinates in units of sigma and energies in
+    units of epsilon."""
     assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
-    if sigma != 1.0 or epsilon != 1.0:
-        E, g = energy_grad(batch, to_reduced(xyz, sigma), precision, grad, stream)
-        E, g, _ = from_reduced(E, g, sigma=sigma, epsilon=epsilon)
-        return E, g
     E = torch.empty(batch.num, dtype=torch.float64, device=xyz.device)
     g = torch.empty_like(xyz) if grad else None
     _order(stream, xyz, E, g, batch.offset)
-    _check(lib().lj_energy_grad_batch(C.byref(batch.desc()), _ptr(xyz), _ptr(E), _ptr(g),
-                                      precision_code(precision), _stream(stream)))
+    _check(lib().lj_energy_grad_batch(C.byref(batch.desc(sigma=sigma, epsilon=epsilon)),
+                                      _ptr(xyz), _ptr(E), _ptr(g), precision_code(precision),
+                                      _stream(stream)))
     return E, g
 
 
@@ -228,22 +216,10 @@ def minimize_workspace_bytes(batch, params=None, precision="fp64"):
 def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, workspace=None,
              stream=None, inplace=False, sigma=1.0, epsilon=1.0):
     """Local minimisation of every cluster; returns a dict of device tensors.
-    params are in reduced units; sigma / epsilon convert the coordinates in and
-    the coordinates, energies and gradient norms out."""
+    Coordinates (in and out) are in units of sigma, energies and gradient norms
+    in units of epsilon (sigma / sigma); params are in reduced units."""
     params = params or lbfgs_params()
     assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.shape == (3, batch.total)
-    if sigma != 1.0 or epsilon != 1.0:
-        out = minimize(batch, to_reduced(xyz, sigma), params, precision, switch_point, workspace,
-                       stream, inplace=True)
-        out["energy"], _, out["xyz"] = from_reduced(out["energy"], xyz=out["xyz"], sigma=sigma,
-                                                    epsilon=epsilon)
-        out["gnorm"] = out["gnorm"] * (epsilon / sigma)
-        if out["xyz_switch"] is not None:
-            out["xyz_switch"] = out["xyz_switch"] * sigma
-        if inplace:
-            xyz.copy_(out["xyz"])
-            out["xyz"] = xyz
-        return out
     dev = xyz.device
     x = xyz if inplace else xyz.clone()
     out = dict(xyz=x, energy=torch.empty(batch.num, dtype=torch.float64, device=dev),
@@ -258,7 +234,8 @@ def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, work
             _check(E_ARG)
         workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
     _order(stream, x, workspace, batch.offset, *out.values())
-    _check(lib().lj_bh_minimize_batch(C.byref(batch.desc()), _ptr(x), _ptr(out["energy"]),
+    _check(lib().lj_bh_minimize_batch(C.byref(batch.desc(sigma=sigma, epsilon=epsilon)),
+                                      _ptr(x), _ptr(out["energy"]),
                                       _ptr(out["gnorm"]), _ptr(out["iters"]), _ptr(out["evals"]),
                                       _ptr(out["status"]), _ptr(out["xyz_switch"]),
                                       C.byref(params), precision_code(precision),
@@ -267,7 +244,7 @@ def minimize(batch, xyz, params=None, precision="fp64", switch_point=False, work
 
 
 def minimize_noalloc(batch, xyz, params=None, precision="fp64", switch_point=False,
-                     stream=None, inplace=False):
+                     stream=None, inplace=False, sigma=1.0, epsilon=1.0):
     """`minimize` through the allocation-free entry point: no workspace, the
     library's fixed per-device scratch instead (at most NOALLOC_MAX_ATOMS atoms
     per cluster and NOALLOC_MAX_CLUSTERS clusters; overlapping calls on one
@@ -284,7 +261,7 @@ def minimize_noalloc(batch, xyz, params=None, precision="fp64", switch_point=Fal
     out["xyz_switch"] = torch.zeros_like(x) if switch_point else None
     _order(stream, x, batch.offset, *out.values())
     _check(lib().lj_bh_minimize_batch_noalloc(
-        C.byref(batch.desc()), _ptr(x), _ptr(out["energy"]), _ptr(out["gnorm"]),
+        C.byref(batch.desc(sigma=sigma, epsilon=epsilon)), _ptr(x), _ptr(out["energy"]), _ptr(out["gnorm"]),
         _ptr(out["iters"]), _ptr(out["evals"]), _ptr(out["status"]), _ptr(out["xyz_switch"]),
         C.byref(params), precision_code(precision), _stream(stream)))
     return out

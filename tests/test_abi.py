@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     L = lj.lib()
-    assert L.lj_abi_version() == 3
+    assert L.lj_abi_version() == 4
     assert L.lj_status_string(lj.OK) == b"LJ_OK"
     for s in (lj.E_ARG, lj.E_HIP, lj.E_WORKSPACE, lj.E_UNSUPPORTED):
         assert L.lj_status_string(s).startswith(b"LJ_E_")
@@ -37,7 +37,8 @@ def test_status_strings_and_version():
 
 def test_pair_selection_is_validated_on_the_host():
     L = lj.lib()
-    assert C.sizeof(lj.Batch) == 48  # int32, ptr, int32, int64, int32, double (natural alignment)
+    # int32, ptr, int32, int64, int32, double, double, double (natural alignment)
+    assert C.sizeof(lj.Batch) == 64
     for pair, rho in ((2, 6.0), (-1, 6.0), (lj.PAIRS["morse"], 0.0), (lj.PAIRS["morse"], -3.0),
                       (lj.PAIRS["morse"], float("nan")), (lj.PAIRS["morse"], float("inf"))):
         b = lj.Batch(2, 16, 13, 26, pair, rho)
@@ -48,6 +49,23 @@ def test_pair_selection_is_validated_on_the_host():
                                        C.byref(p), lj.FP64, None, 0, None) == lj.E_ARG)
     with pytest.raises(ValueError):
         lj.ClusterBatch([0, 3], device="cpu", pair="buckingham")
+
+
+def test_units_are_validated_on_the_host():
+    L = lj.lib()
+    p = lj.lbfgs_params()
+    for sg, ep in ((-1.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        b = lj.Batch(2, 16, 13, 26, 0, 0.0, sg, ep)
+        assert L.lj_energy_grad_batch(C.byref(b), 16, 16, None, lj.FP64, None) == lj.E_ARG
+        assert b"sigma" in L.lj_last_error()
+    # basin hopping runs in reduced units only
+    b = lj.Batch(2, 16, 13, 26, 0, 0.0, 2.0, 1.0)
+    bh = lj.bh_params()
+    assert L.lj_bh_workspace_bytes(C.byref(b), C.byref(bh), C.byref(p), lj.FP64) == 0
+    st = lj.BhState(*([16] * 8))
+    assert (L.lj_bh_step(C.byref(b), C.byref(st), C.byref(bh), C.byref(p), lj.FP64, 1, None,
+                         16, 1 << 20, None) == lj.E_UNSUPPORTED)
+    assert b"reduced units" in L.lj_last_error()
 
 
 def test_defaults():
