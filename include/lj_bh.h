@@ -335,7 +335,8 @@ lj_status lj_get_schedule(int32_t kind, int32_t precision, int32_t max_n, int32_
  * and 0 in turn, each timed on a whole minimisation of a copy of xyz (default
  * parameters, at most 1000 iterations per phase) with the other classes at
  * their current choice, a shape replacing the current one when at least 2 %
- * faster.  xyz [3][total_atoms] is read only.  Unlike every other call this
+ * faster.  Every candidate is timed as the median of five launches after a
+ * warm-up.  xyz [3][total_atoms] is read only.  Unlike every other call this
  * one SYNCHRONISES the stream (it times launches with HIP events).
  *   ws, ws_bytes     scratch of at least lj_autotune_workspace_bytes().
  *   best_eval_ms     fastest pair-kernel time (nullable).

@@ -2,6 +2,7 @@
 // scheduling and the HIP-graph cache of the basin-hopping step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <cmath>
@@ -937,20 +938,22 @@ lj_status lj_autotune(const lj_batch* batch, const double* xyz, int32_t precisio
     LJ_HIP_TRY(hipEventCreate(&evs.e[0]));
     LJ_HIP_TRY(hipEventCreate(&evs.e[1]));
     hipEvent_t e0 = evs.e[0], e1 = evs.e[1];
+    // median of five timed launches after a warm-up (a minimum would follow
+    // the luckiest launch of a shape whose launches vary)
     auto time_it = [&](auto&& launch, float& ms) -> lj_status {
         lj_status r = launch();  // warm-up
         if (r != LJ_OK) return r;
-        float best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        constexpr int kReps = 5;
+        float t[kReps];
+        for (int rep = 0; rep < kReps; ++rep) {
             LJ_HIP_TRY(hipEventRecord(e0, st));
             if ((r = launch()) != LJ_OK) return r;
             LJ_HIP_TRY(hipEventRecord(e1, st));
             LJ_HIP_TRY(hipEventSynchronize(e1));
-            float t = 0.f;
-            LJ_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-            if (t < best) best = t;
+            LJ_HIP_TRY(hipEventElapsedTime(&t[rep], e0, e1));
         }
-        ms = best;
+        std::sort(t, t + kReps);
+        ms = t[kReps / 2];
         return LJ_OK;
     };
     // pair kernel: every shape holding max_n atoms without more than doubling the padding
