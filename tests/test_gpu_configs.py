@@ -57,7 +57,9 @@ def test_lj38_1024_mixed_polish_every_cluster():
     ref = O.minimize(off, x, oracle_params(p))  # FP64 from the same starts
     same = np.abs(r["energy"] - ref["energy"]) <= 1e-6 * np.abs(ref["energy"])
     announce(f"mixed vs fp64 same minimum: {same.mean():.3f}")
-    assert same.mean() > 0.5  # trajectory-level agreement is statistical (FP32 rounding)
+    # trajectory-level agreement is statistical (FP32 rounding moves some starts into
+    # other basins); the measured share is 0.699 (716 of 1024)
+    assert same.mean() > 0.69
 
 
 def oracle_minimize_pool(off, x, params):
