@@ -152,3 +152,35 @@ def test_autotuned_shapes_keep_parity(tmp_path, precision):
         for c in range(3):
             reset(c, precision, b.max_n)
         lj.set_schedule(lj.SCHED_EVAL, precision, b.max_n, *lj.eval_shape_default(b.max_n))
+
+
+@pytest.mark.parametrize("shape", [2, 3])
+def test_packed_degenerate_clusters(shape):
+    """Packed teams with coincident atoms (non-finite energy, which also takes
+    the evaluation's IEEE-division repeat), an empty and a one-atom cluster
+    and a far-apart pair, beside ordinary ones: every output equals the
+    oracle's bit for bit (FP64), and the mixed statuses match."""
+    sizes = [5, 0, 1, 2, 13, 16, 3, 9, 11]
+    off, x = random_starts(sizes, 8601)
+    x = x.copy()
+    x[:, 1] = x[:, 0]                 # cluster 0: atoms 0 and 1 coincide
+    o = off[3]
+    x[:, o + 1] = x[:, o] + [1e7, 0.0, 0.0]  # cluster 3: a pair 1e7 apart
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params()
+    ro = O.minimize(off, x, oracle_params(p))
+    try:
+        for prec in ("fp64", "mixed"):
+            announce(f"packed degenerate clusters shape {shape} {prec}")
+            forced(0, prec, b.max_n, shape)
+            r = host_dict(lj.minimize(b, xd, p, prec))
+            assert r["status"][0] == lj.NONFINITE and r["status"][1] == lj.CONVERGED
+            assert r["energy"][1] == 0.0 and r["energy"][2] == 0.0 and r["iters"][2] == 0
+            if prec == "fp64":
+                for key in KEYS:
+                    assert np.array_equal(r[key], ro[key], equal_nan=True), key
+            else:
+                assert np.array_equal(r["status"], ro["status"])
+    finally:
+        reset(0, "fp64", b.max_n)
+        reset(0, "mixed", b.max_n)
