@@ -184,3 +184,35 @@ def test_packed_degenerate_clusters(shape):
     finally:
         reset(0, "fp64", b.max_n)
         reset(0, "mixed", b.max_n)
+
+
+def test_packed_candidates_in_mixed_bh_chains():
+    """Mixed LJ13 chains whose candidates run the FP32 phase only (no polish)
+    four per wavefront: the oracle's selection, Metropolis and adaptation,
+    fed the GPU's candidate energies, take the same decisions; every accepted
+    candidate's FP64 polish converges and the current structures are minima
+    to oracle ||g|| < 1e-6 with the reported energies."""
+    from test_gpu_bh import replay_decisions
+    sizes, steps = [13] * 24, 20
+    off, b, r, p = start_chains(sizes, 8701)
+    bh = lj.bh_params(cands=8, kT=0.8, seed=8701)
+    try:
+        forced(0, "mixed", 13, 3)
+        announce("bh mixed 24 x LJ13 x 8 candidates, four clusters per wavefront")
+        bhx = lj.BasinHopping(b, r["xyz"], r["energy"], bh, p, "mixed", trace_steps=steps,
+                              trace_candidates=True)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            bhx.step(steps)
+        side.synchronize()
+    finally:
+        reset(0, "mixed", 13)
+    torch.cuda.synchronize()
+    tr = {k: (None if v is None else v.cpu().numpy()) for k, v in bhx.trace.items()}
+    replay_decisions(tr, r["energy"].cpu().numpy(), bh)
+    acc = tr["accepted"] == 1
+    assert np.all(tr["polish_status"][acc] == lj.CONVERGED)
+    Eo, go = O.energy_grad(off, host(bhx.xyz_cur))
+    assert np.array_equal(Eo, host(bhx.e_cur))
+    gn = np.sqrt(np.add.reduceat((go * go).sum(axis=0), off[:-1]))
+    assert np.all(gn < 1e-6)
