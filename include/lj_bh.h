@@ -306,7 +306,9 @@ lj_status lj_bh_step(const lj_batch* chains, const lj_bh_state* state, const lj_
  *                                 cluster reduced over one 16-lane row
  *                                 (N <= 16), 2 two clusters per wavefront
  *                                 (N <= 32), 3 four clusters per wavefront
- *                                 (N <= 16);
+ *                                 (N <= 16); 4-7 shapes 0-3 compiled to run
+ *                                 two wavefronts per SIMD (registers capped
+ *                                 at 256, the rest spilled);
  *                        class 1: w = 0 two wavefronts, 1 one wavefront with
  *                                 two atoms per lane;
  *                        class 2: w = 0 four wavefronts, 1 three wavefronts

@@ -182,9 +182,20 @@ int default_class_shape(int c, int max_n, int top_class, int mixed, int num, int
         // waits for its slowest cluster, and a packed wavefront waits for the
         // slowest of its clusters, so one cluster per wavefront is as fast.
         const bool many = num > 2 * 4 * cus;
-        if (cmax <= 16) return many ? 3 : 1;
-        if (cmax <= 32 && many) return 2;
-        return 0;
+        int shape = 0;
+        if (cmax <= 16)
+            shape = many ? 3 : 1;
+        else if (cmax <= 32 && many)
+            shape = 2;
+        // Two wavefronts per SIMD (registers capped, some spilled) once the
+        // call holds only this class and has more wavefronts than SIMDs: the
+        // second wavefront fills the first one's issue gaps (2048 x LJ38
+        // mixed: 3.85 instead of 4.39 ms; 16384 x LJ13: 1.82 instead of 2.27
+        // ms FP64), while with one wavefront per SIMD the spills only cost.
+        const long waves = ((long)num + lj::shape_clusters_per_wg(0, shape) - 1) /
+                           lj::shape_clusters_per_wg(0, shape);
+        if (top_class == 0 && waves > 4L * cus) shape += 4;
+        return shape;
     }
     if (c == 2) return cmax <= 192 ? 1 : 0; // three wavefronts
     // Class 1 as one wavefront with two atoms per lane: about 1.5 times the

@@ -638,8 +638,9 @@ __device__ int lbfgs_run(Team<W, A, POT, L, G>& tm, History<W, A, HREG>& H, doub
 // one per packed team of 64 / G lanes) and minimises it; it claims again once
 // all of its teams are done.
 // ---------------------------------------------------------------------------
-template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1>
-__global__ __launch_bounds__(kWave* W) void minimize_kernel(MinArgs args) {
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1, int OCC = 1>
+__global__ __launch_bounds__(kWave* W) __attribute__((amdgpu_waves_per_eu(OCC))) void minimize_kernel(
+    MinArgs args) {
     constexpr int T = kWave * W;
     constexpr int LG = kWave / G;  // lanes of a packed team
     __shared__ double4 pos_buf[T * A];
@@ -921,6 +922,9 @@ hipError_t launch_energy_grad(int mixed, int pot, EvalShape s, int num, const in
 //                           (N <= 16)
 //                        2  two clusters per wavefront, 32 lanes each (N <= 32)
 //                        3  four clusters per wavefront, 16 lanes each (N <= 16)
+//                        4-7  shapes 0-3 compiled for two wavefronts per SIMD
+//                           (at most 256 registers, the rest spilled): for
+//                           batches of more wavefronts than SIMDs
 //   class 1 (N <= 128):  0  two wavefronts;  1  one wavefront, two atoms per lane
 //   class 2 (N <= 256):  0  four wavefronts;  1  three wavefronts (N <= 192)
 //   class 3 (N <= 1024): 0  16 wavefronts x 1 atom, 1  8 x 2, 2  4 x 4
@@ -930,12 +934,14 @@ struct ClassShape {
     int G;     // clusters per workgroup
     int max_n; // largest cluster the shape holds
 };
-constexpr int kShapes[kNumClasses] = {4, 2, 2, 3};
-constexpr ClassShape kShape[kNumClasses][4] = {
-    {{1, 1, true, 1, 64}, {1, 1, true, 1, 16}, {1, 1, true, 2, 32}, {1, 1, true, 4, 16}},
-    {{2, 1, true, 1, 128}, {1, 2, true, 1, 128}, {}, {}},
-    {{4, 1, true, 1, 256}, {3, 1, true, 1, 192}, {}, {}},
-    {{16, 1, false, 1, 1024}, {8, 2, false, 1, 1024}, {4, 4, false, 1, 1024}, {}}};
+constexpr int kMaxShapes = 8;
+constexpr int kShapes[kNumClasses] = {8, 2, 2, 3};
+constexpr ClassShape kShape[kNumClasses][kMaxShapes] = {
+    {{1, 1, true, 1, 64}, {1, 1, true, 1, 16}, {1, 1, true, 2, 32}, {1, 1, true, 4, 16},
+     {1, 1, true, 1, 64}, {1, 1, true, 1, 16}, {1, 1, true, 2, 32}, {1, 1, true, 4, 16}},
+    {{2, 1, true, 1, 128}, {1, 2, true, 1, 128}},
+    {{4, 1, true, 1, 256}, {3, 1, true, 1, 192}},
+    {{16, 1, false, 1, 1024}, {8, 2, false, 1, 1024}, {4, 4, false, 1, 1024}}};
 
 int class_shapes(int c) { return c >= 0 && c < kNumClasses ? kShapes[c] : 0; }
 int shape_max_n(int c, int shape) { return kShape[c][shape].max_n; }
@@ -952,25 +958,29 @@ size_t class_hist_bytes_per_wg(int c, int shape) {
     return s.hreg ? 0 : (size_t)2 * kMaxM * 3 * s.A * kWave * s.W * sizeof(double);
 }
 
-template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1>
+template <int MIXED, int W, int A, bool HREG, int POT, int L = kWave, int G = 1, int OCC = 1>
 static const void* min_kernel_ptr() {
-    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT, L, G>);
+    return reinterpret_cast<const void*>(&minimize_kernel<MIXED, W, A, HREG, POT, L, G, OCC>);
 }
 
 template <int MIXED, int POT>
 static const void* minimize_kernel_pm(int c, int shape) {
-    switch (c * 4 + shape) {
+    switch (c * kMaxShapes + shape) {
         case 0: return min_kernel_ptr<MIXED, 1, 1, true, POT>();
         case 1: return min_kernel_ptr<MIXED, 1, 1, true, POT, 16>();
         case 2: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 2>();
         case 3: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 4>();
-        case 4: return min_kernel_ptr<MIXED, 2, 1, true, POT>();
-        case 5: return min_kernel_ptr<MIXED, 1, 2, true, POT>();
-        case 8: return min_kernel_ptr<MIXED, 4, 1, true, POT>();
-        case 9: return min_kernel_ptr<MIXED, 3, 1, true, POT>();
-        case 12: return min_kernel_ptr<MIXED, 16, 1, false, POT>();
-        case 13: return min_kernel_ptr<MIXED, 8, 2, false, POT>();
-        case 14: return min_kernel_ptr<MIXED, 4, 4, false, POT>();
+        case 4: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 1, 2>();
+        case 5: return min_kernel_ptr<MIXED, 1, 1, true, POT, 16, 1, 2>();
+        case 6: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 2, 2>();
+        case 7: return min_kernel_ptr<MIXED, 1, 1, true, POT, kWave, 4, 2>();
+        case kMaxShapes + 0: return min_kernel_ptr<MIXED, 2, 1, true, POT>();
+        case kMaxShapes + 1: return min_kernel_ptr<MIXED, 1, 2, true, POT>();
+        case 2 * kMaxShapes + 0: return min_kernel_ptr<MIXED, 4, 1, true, POT>();
+        case 2 * kMaxShapes + 1: return min_kernel_ptr<MIXED, 3, 1, true, POT>();
+        case 3 * kMaxShapes + 0: return min_kernel_ptr<MIXED, 16, 1, false, POT>();
+        case 3 * kMaxShapes + 1: return min_kernel_ptr<MIXED, 8, 2, false, POT>();
+        case 3 * kMaxShapes + 2: return min_kernel_ptr<MIXED, 4, 4, false, POT>();
     }
     return nullptr;
 }

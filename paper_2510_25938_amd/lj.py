@@ -21,7 +21,7 @@ MAX_ATOMS_EVAL, MAX_ATOMS_MIN, MAX_M, MAX_CANDS = 4096, 1024, 10, 64
 SCHED_EVAL, SCHED_MIN_LARGE = 0, 1
 SCHED_MIN_CLASS = (2, 3, 4)  # minimiser shape of size classes 0, 1, 2
 # shapes per class: (clusters per workgroup, largest N) for each shape index
-CLASS_SHAPES = {0: ((1, 64), (1, 16), (2, 32), (4, 16)), 1: ((1, 128), (1, 128)),
+CLASS_SHAPES = {0: ((1, 64), (1, 16), (2, 32), (4, 16)) * 2, 1: ((1, 128), (1, 128)),
                 2: ((1, 256), (1, 192))}
 EXPORTED = ["lj_energy_grad_batch", "lj_lbfgs_defaults", "lj_minimize_workspace_bytes",
             "lj_bh_minimize_batch", "lj_bh_workspace_bytes", "lj_bh_step", "lj_set_schedule",

@@ -171,13 +171,16 @@ def test_class_schedule_validation():
     assert lj.get_schedule(c0, "fp64", 13) == (-1, 0)  # no entry: the built-in rule
     assert L.lj_set_schedule(c0, lj.FP64, 40, 3, 0) == lj.E_ARG  # four per wave holds <= 16
     assert b"holds at most 16" in L.lj_last_error()
-    assert L.lj_set_schedule(c0, lj.FP64, 40, 4, 0) == lj.E_ARG  # no shape 4
+    assert L.lj_set_schedule(c0, lj.FP64, 40, 7, 0) == lj.E_ARG  # four per wave, 2 per SIMD
+    assert L.lj_set_schedule(c0, lj.FP64, 40, 8, 0) == lj.E_ARG  # no shape 8
     assert L.lj_set_schedule(c2, lj.FP64, 100, 0, 0) == lj.E_ARG  # no class-2 clusters
     assert L.lj_set_schedule(c2, lj.FP64, 250, 1, 0) == lj.E_ARG  # three waves hold <= 192
     lj.set_schedule(c0, "fp64", 13, 3)
     assert lj.get_schedule(c0, "fp64", 13) == (3, 4)
     assert lj.get_schedule(c0, "fp64", 9) == (3, 4)  # same power-of-two key
     assert lj.get_schedule(c0, "mixed", 13) == (-1, 0)
+    lj.set_schedule(c0, "fp64", 13, 7)
+    assert lj.get_schedule(c0, "fp64", 13) == (7, 4)
     lj.set_schedule(c0, "fp64", 13, -1)
     assert lj.get_schedule(c0, "fp64", 13) == (-1, 0)
     lj.set_schedule(c1, "mixed", 150, 1)

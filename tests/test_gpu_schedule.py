@@ -38,7 +38,8 @@ SMALL = [0, 1, 2, 3] + list(uniform_sizes(301, 4, 16, 8101))
 MID = [0, 1, 17] + list(uniform_sizes(257, 2, 32, 8102))
 
 
-@pytest.mark.parametrize("sizes,shapes", [(SMALL, (0, 1, 2, 3)), (MID, (0, 2))])
+# shapes 4-7 are shapes 0-3 compiled for two wavefronts per SIMD
+@pytest.mark.parametrize("sizes,shapes", [(SMALL, tuple(range(8))), (MID, (0, 2, 4, 6))])
 @pytest.mark.parametrize("pair", ["lj", "morse"])
 def test_class0_shapes_fp64_bitwise(sizes, shapes, pair):
     off, x = random_starts(sizes, 8103 + len(sizes))
@@ -60,7 +61,7 @@ def test_class0_shapes_fp64_bitwise(sizes, shapes, pair):
     assert np.all(ro["status"] == lj.CONVERGED)
 
 
-@pytest.mark.parametrize("sizes,shapes", [(SMALL, (0, 1, 2, 3)), (MID, (0, 2))])
+@pytest.mark.parametrize("sizes,shapes", [(SMALL, tuple(range(8))), (MID, (0, 2, 4, 6))])
 def test_class0_shapes_mixed_polish_bitwise(sizes, shapes):
     off, x = random_starts(sizes, 8203 + len(sizes))
     b, xd = to_dev(off, x)
@@ -154,7 +155,7 @@ def test_autotuned_shapes_keep_parity(tmp_path, precision):
         lj.set_schedule(lj.SCHED_EVAL, precision, b.max_n, *lj.eval_shape_default(b.max_n))
 
 
-@pytest.mark.parametrize("shape", [2, 3])
+@pytest.mark.parametrize("shape", [2, 3, 6, 7])
 def test_packed_degenerate_clusters(shape):
     """Packed teams with coincident atoms (non-finite energy, which also takes
     the evaluation's IEEE-division repeat), an empty and a one-atom cluster
@@ -216,3 +217,17 @@ def test_packed_candidates_in_mixed_bh_chains():
     assert np.array_equal(Eo, host(bhx.e_cur))
     gn = np.sqrt(np.add.reduceat((go * go).sum(axis=0), off[:-1]))
     assert np.all(gn < 1e-6)
+
+
+def test_default_rule_two_waves_per_simd_fp64_bitwise():
+    """A one-class batch of more clusters than SIMDs: the built-in rule runs
+    class 0 two wavefronts per SIMD; every FP64 output equals the oracle's."""
+    sizes = list(uniform_sizes(1100, 30, 40, 8801))
+    off, x = random_starts(sizes, 8802)
+    b, xd = to_dev(off, x)
+    p = lj.lbfgs_params()
+    announce(f"default rule fp64 {b.num} clusters N 30..40")
+    r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    ro = O.minimize(off, x, oracle_params(p))
+    for key in KEYS:
+        assert np.array_equal(r[key], ro[key]), key
