@@ -254,7 +254,8 @@ lj_status min_layout(int num, int max_n, int mixed, int pot, MinLayout& L,
     auto grid_for = [&](int c, int shape, int& g_out) -> lj_status {
         int per_cu = 0;
         LJ_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, lj::minimize_kernel_for(mixed, pot, c, shape), lj::class_block(c, shape), 0));
+            &per_cu, lj::minimize_kernel_for(mixed, pot, c, shape), lj::class_block(c, shape),
+            lj::class_dyn_lds(c, shape, max_n, pot)));
         if (per_cu < 1) per_cu = 1;
         const int per_wg = lj::shape_clusters_per_wg(c, shape);
         long g = (long)per_cu * di.cus;
@@ -352,6 +353,8 @@ lj_status enqueue_minimize(const lj_batch* b, const int32_t* active, double* xyz
     a.pot = b->pair;
     a.rho = b->pair_rho;
     a.u = units_of(b);
+    a.max_n = b->max_n;
+    a.up_n = 0;
     if (L.top_class == 0) {
         a.cls = 0;
         a.hist = nullptr;

@@ -441,6 +441,19 @@ __device__ __forceinline__ void pair_morse64(const double4 p, bool self, double 
     gz = fma(f, dz, gz);
 }
 
+// The FP64 Morse terms of one distinct pair, with the operations of
+// pair_morse64: .y = V and .x = the gradient coefficient, functions of r2
+// alone.
+__device__ __forceinline__ double2 term_morse64(double dx, double dy, double dz, double rho,
+                                                double c) {
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double r = sqrt(r2);
+    const double t = exp_cw(fma(-rho, r, rho));
+    const double et = t * (t - 2.0);
+    const double fn = (c * t) * (t - 1.0);
+    return make_double2(fn / r, et);
+}
+
 // FP32: hardware square root, base-2 exponential and reciprocal.
 __device__ __forceinline__ void pair_morse32(const float4 p, bool self, float xi, float yi,
                                              float zi, float rho, float c, float& e, float& gx,
@@ -505,6 +518,108 @@ __device__ __forceinline__ void pairs_fp64(int n, const double4* __restrict__ po
 #pragma unroll
         for (int a = 0; a < A; ++a) pair(p, j == a * T + t, a);
     }
+}
+
+// FP64 Morse pair, one wavefront, one atom per lane (lane t holds atom t):
+// every unique pair's terms once, then the oracle's ordered sums.  A Morse
+// term (an exponential, a square root and a division) costs far more than
+// the matrix's LDS traffic; the cheaper terms of Eq. (1) stay in the ordered
+// loop, which is as fast for them.
+//   1. The n (n - 1) / 2 unique pairs, listed once per cluster by
+//      up_pair_list, go to the lanes in turn, 64 at a time.  Each pair's
+//      (f, e term) is written to both slots M[i n + j] and M[j n + i] of an
+//      n x n LDS matrix; the diagonal holds zeros.
+//   2. Lane i adds M[j n + i] for j = 0 .. n - 1 in ascending order into
+//      e_i and g_i = sum f (x_i - x_j), with x_i - x_j formed as in the
+//      ordered loop.
+// The terms depend on r2 only, which is the same from either side of a pair,
+// so every sum sees the same terms in the same order as pairs_fp64: the
+// results are bitwise equal, for half the pair terms.
+
+// The pair list: entry p = (k - 1) n + i (ring order: atom i and partner
+// (i + k) mod n, k = 1 .. n / 2; for even n the last distance on i < n / 2
+// only) holds the byte offsets of both atoms in pos (x) and of both matrix
+// slots (y), 16 bits each.  (p + 1/2) / n is at least 1 / (2 n) away from an
+// integer, far more than the FP32 rounding of the product for p < 2^12, so
+// its truncation is p / n exactly.  One wavefront; n <= 64.
+__device__ __forceinline__ void up_pair_list(int n, uint2* __restrict__ list, int t) {
+    const int P = n * (n - 1) / 2;
+    if (P <= 0) return;
+    const float inv_n = 1.0f / (float)n;
+    for (int p = t; p < P; p += kWave) {
+        const int k1 = (int)(((float)p + 0.5f) * inv_n);  // k - 1
+        const int i = p - k1 * n;
+        int j = i + k1 + 1;
+        j = j >= n ? j - n : j;
+        list[p] = make_uint2((uint32_t)(i * 32) | ((uint32_t)(j * 32) << 16),
+                             (uint32_t)((i * n + j) * 16) | ((uint32_t)((j * n + i) * 16) << 16));
+    }
+}
+
+constexpr int kUpRounds = 4;
+
+__device__ __forceinline__ void pairs_morse64_up(int n, const double4* __restrict__ pos,
+                                                 double2* __restrict__ M,
+                                                 const uint2* __restrict__ list,
+                                                 const double (&x)[3][1], double (&e)[1],
+                                                 double (&g)[3][1], double rho, int t) {
+    const double c = -2.0 * rho;
+    const int P = n * (n - 1) / 2;
+    const char* pb = reinterpret_cast<const char*>(pos);
+    char* mb = reinterpret_cast<char*>(M);
+    if (t < n) M[t * n + t] = make_double2(0.0, 0.0);
+    // kUpRounds rounds of 64 pairs at a time, so that their LDS reads and
+    // arithmetic overlap; entries past the list repeat its last one and are
+    // not stored
+    const int R = (P + kWave - 1) / kWave;
+    for (int r0 = 0; r0 < R; r0 += kUpRounds) {
+        uint2 w[kUpRounds];
+        double4 pi[kUpRounds], pj[kUpRounds];
+        double2 tt[kUpRounds];
+#pragma unroll
+        for (int u = 0; u < kUpRounds; ++u) w[u] = list[min(t + kWave * (r0 + u), P - 1)];
+#pragma unroll
+        for (int u = 0; u < kUpRounds; ++u) {
+            pi[u] = *reinterpret_cast<const double4*>(pb + (w[u].x & 0xffffu));
+            pj[u] = *reinterpret_cast<const double4*>(pb + (w[u].x >> 16));
+        }
+#pragma unroll
+        for (int u = 0; u < kUpRounds; ++u)
+            tt[u] = term_morse64(pi[u].x - pj[u].x, pi[u].y - pj[u].y, pi[u].z - pj[u].z, rho, c);
+#pragma unroll
+        for (int u = 0; u < kUpRounds; ++u)
+            if (t + kWave * (r0 + u) < P) {
+                *reinterpret_cast<double2*>(mb + (w[u].y & 0xffffu)) = tt[u];
+                *reinterpret_cast<double2*>(mb + (w[u].y >> 16)) = tt[u];
+            }
+    }
+    __syncthreads();  // one wavefront: the matrix is complete
+    e[0] = 0.0;
+    g[0][0] = g[1][0] = g[2][0] = 0.0;
+    const double xi = x[0][0], yi = x[1][0], zi = x[2][0];
+    const double2* Mi = M + (t < n ? t : (n > 0 ? n - 1 : 0));  // lanes >= n: results unused
+    auto acc = [&](const double4 p, const double2 tt) {
+        const double dx = xi - p.x;
+        const double dy = yi - p.y;
+        const double dz = zi - p.z;
+        e[0] = e[0] + tt.y;
+        g[0][0] = fma(tt.x, dx, g[0][0]);
+        g[1][0] = fma(tt.x, dy, g[1][0]);
+        g[2][0] = fma(tt.x, dz, g[2][0]);
+    };
+    int j = 0;
+    for (; j + kGroup64 <= n; j += kGroup64) {
+        double4 p[kGroup64];
+        double2 tt[kGroup64];
+#pragma unroll
+        for (int u = 0; u < kGroup64; ++u) {
+            p[u] = pos[j + u];
+            tt[u] = Mi[(j + u) * n];
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup64; ++u) acc(p[u], tt[u]);
+    }
+    for (; j < n; ++j) acc(pos[j], Mi[j * n]);
 }
 
 // FP32 pair arithmetic and FP32 accumulation over tiles of kTileJ partners;

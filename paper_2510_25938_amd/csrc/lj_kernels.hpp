@@ -61,6 +61,8 @@ struct MinArgs {
     int pot;            // LJ_PAIR_LJ or LJ_PAIR_MORSE
     double rho;         // Morse range
     Units u;
+    int max_n;          // the batch's largest cluster
+    int up_n;           // set by launch_minimize_class (class_up_n)
 };
 
 // Launchers (lj_minimize.hip, lj_bh_kernels.hip).
@@ -81,6 +83,13 @@ int class_shapes(int c);
 int shape_max_n(int c, int shape);
 int shape_clusters_per_wg(int c, int shape);
 int class_block(int c, int shape);
+// Largest N that the unique-pair FP64 evaluation (Morse pair) serves in a
+// launch of this shape on a batch of at most max_n atoms (0: none), and the
+// dynamic LDS it takes (an up_n x up_n matrix of double2 and the list of the
+// pairs).
+constexpr int kUpMaxN = 40;
+int class_up_n(int c, int shape, int max_n, int pot);
+size_t class_dyn_lds(int c, int shape, int max_n, int pot);
 size_t class_hist_bytes_per_wg(int c, int shape);
 const void* minimize_kernel_for(int mixed, int pot, int c, int shape);
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,

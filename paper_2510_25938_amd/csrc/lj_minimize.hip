@@ -26,9 +26,14 @@ namespace lj {
 // wavefront-uniform scalar; LDS order within one wavefront needs no barrier
 // (a wavefront's LDS instructions execute in issue order).
 // ---------------------------------------------------------------------------
-template <int W, int A, int POT, int L = kWave, int G = 1>
+// UP (Morse pair): the FP64 evaluation takes the unique-pair form
+// (pairs_morse64_up) for clusters of at most up_n atoms, with an up_n x up_n
+// pair matrix at upm.
+template <int W, int A, int POT, int L = kWave, int G = 1, bool UP = false>
 struct Team {
     static_assert(G == 1 || (W == 1 && A == 1 && L == kWave), "packing: one wavefront, one slot");
+    static_assert(!UP || (W == 1 && A == 1 && G == 1 && POT == kPairMorse),
+                  "unique pairs: Morse pair, one wavefront, one cluster");
     static constexpr int T = kWave * W;
     static constexpr int NVMAX = 4 * A;
     static constexpr int kG = G;
@@ -40,6 +45,19 @@ struct Team {
     int n;
     int li;      // atom index of this thread's slot 0 within the cluster
     double rho;  // Morse range (POT == kPairMorse)
+    double2* upm;    // up_n x up_n pair matrix
+    uint2* uplist;   // up_n (up_n - 1) / 2 pair-list entries
+    int up_n;
+
+    // Before the first evaluation of a cluster (n set): its pair list.
+    __device__ __forceinline__ void prepare() {
+        if constexpr (UP) {
+            if (n <= up_n) {
+                up_pair_list(n, uplist, li);
+                __syncthreads();
+            }
+        }
+    }
 
     __device__ __forceinline__ bool active(int a) const { return a * T + li < n; }
 
@@ -205,7 +223,7 @@ struct Team {
         } else if constexpr (F32) {
             pairs_mixed<A, T, POT>(n, pos32, x, e[0], g, rho, li);
         } else {
-            pairs_fp64<A, T, POT, POT == kPairMorse>(n, pos64, x, e[0], g, rho, li);
+            fp64_pairs<POT == kPairMorse>(x, e[0], g);
         }
 #pragma unroll
         for (int a = 0; a < A; ++a)
@@ -216,7 +234,7 @@ struct Team {
             // 1/r2 differ from the IEEE quotient, and it makes E not finite:
             // then the evaluation is repeated with the IEEE division
             if (!isfinite(o[0])) {
-                pairs_fp64<A, T, POT, true>(n, pos64, x, e[0], g, rho, li);
+                fp64_pairs<true>(x, e[0], g);
 #pragma unroll
                 for (int a = 0; a < A; ++a)
                     if (!active(a)) e[0][a] = g[0][a] = g[1][a] = g[2][a] = 0.0;
@@ -224,6 +242,18 @@ struct Team {
             }
         }
         return (POT == kPairMorse ? 0.5 : 2.0) * o[0];
+    }
+
+    template <bool IEEE>
+    __device__ __forceinline__ void fp64_pairs(const double (&x)[3][A], double (&e)[A],
+                                               double (&g)[3][A]) {
+        if constexpr (UP) {
+            if (n <= up_n) {
+                pairs_morse64_up(n, pos64, upm, uplist, x, e, g, rho, li);
+                return;
+            }
+        }
+        pairs_fp64<A, T, POT, IEEE>(n, pos64, x, e, g, rho, li);
     }
 
     __device__ __forceinline__ void sum_energy(double (&e)[1][A], double (&o)[1]) {
@@ -451,8 +481,8 @@ constexpr double kNoiseZone = 100.0;
 constexpr int kZonePatience = 30;
 
 // E and g at x with FP32 pair arithmetic when f32 (only compiled when CAN32).
-template <bool CAN32, int W, int A, int POT, int L, int G>
-__device__ __forceinline__ double eval_phase(Team<W, A, POT, L, G>& tm, const double (&x)[3][A],
+template <bool CAN32, int W, int A, int POT, int L, int G, bool UP>
+__device__ __forceinline__ double eval_phase(Team<W, A, POT, L, G, UP>& tm, const double (&x)[3][A],
                                              double (&g)[3][A], bool f32) {
     if constexpr (CAN32) {
         if (f32) return tm.template eval<true>(x, g);
@@ -465,8 +495,8 @@ __device__ __forceinline__ double eval_phase(Team<W, A, POT, L, G>& tm, const do
 // single copy of this loop for both phases) selects the FP32 pair arithmetic,
 // the Armijo noise allowance and the stall exit of the mixed path's first
 // phase.
-template <bool CAN32, int W, int A, bool HREG, int POT, int L, int G>
-__device__ int lbfgs_run(Team<W, A, POT, L, G>& tm, History<W, A, HREG>& H, double (&x)[3][A],
+template <bool CAN32, int W, int A, bool HREG, int POT, int L, int G, bool UP>
+__device__ int lbfgs_run(Team<W, A, POT, L, G, UP>& tm, History<W, A, HREG>& H, double (&x)[3][A],
                          double (&g)[3][A], double& E, double& gnorm, int& iters, int& evals,
                          const LbfgsDev& p, double gtol, int max_iter, bool f32_flag) {
     const bool F32 = CAN32 && f32_flag;
@@ -651,8 +681,17 @@ __global__ __launch_bounds__(kWave* W) __attribute__((amdgpu_waves_per_eu(OCC)))
                                    ? 6 * T * A
                                    : 1];
 
+    // one-wavefront, one-cluster Morse kernels at one wavefront per SIMD take
+    // the unique-pair FP64 evaluation, with its matrix in dynamic LDS (for
+    // Eq. (1) the ordered loop is as fast: its pair terms are too cheap to
+    // pay for the matrix's LDS traffic)
+    constexpr bool kUp = W == 1 && A == 1 && G == 1 && OCC == 1 && POT == kPairMorse;
+    extern __shared__ double2 up_matrix[];
     const int team = G > 1 ? (int)threadIdx.x / LG : 0;
-    Team<W, A, POT, L, G> tm;
+    Team<W, A, POT, L, G, kUp> tm;
+    tm.upm = up_matrix;
+    tm.up_n = kUp ? args.up_n : 0;
+    tm.uplist = reinterpret_cast<uint2*>(up_matrix + (size_t)tm.up_n * tm.up_n);
     tm.li = G > 1 ? (int)threadIdx.x % LG : (int)threadIdx.x;
     tm.pos64 = pos_buf + team * LG;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf) + team * LG;
@@ -679,6 +718,7 @@ __global__ __launch_bounds__(kWave* W) __attribute__((amdgpu_waves_per_eu(OCC)))
         const int o = has ? args.offset[b] : 0;
         const int n = has ? args.offset[b + 1] - o : 0;
         tm.n = n;  // the plan guarantees 0 <= n <= T*A (G > 1: <= 64 / G)
+        tm.prepare();
 
         double x[3][A], g[3][A];
 #pragma unroll
@@ -824,6 +864,9 @@ __global__ __launch_bounds__(kWave* W) void energy_grad_kernel(const int32_t* of
         return;
     }
     Team<W, A, POT> tm;
+    tm.upm = nullptr;
+    tm.uplist = nullptr;
+    tm.up_n = 0;
     tm.pos64 = pos_buf;
     tm.pos32 = reinterpret_cast<float4*>(pos_buf);
     tm.rbuf = tile_rbuf;
@@ -995,6 +1038,22 @@ const void* minimize_kernel_for(int mixed, int pot, int c, int shape) {
 
 int class_block(int c, int shape) { return kWave * kShape[c][shape].W; }
 
+int class_up_n(int c, int shape, int max_n, int pot) {
+    if (pot != kPairMorse || c < 0 || c >= kNumClasses || shape < 0 || shape >= kShapes[c])
+        return 0;
+    const ClassShape s = kShape[c][shape];
+    // the one-wavefront, one-cluster shapes at one wavefront per SIMD
+    if (!(s.W == 1 && s.A == 1 && s.G == 1 && !(c == 0 && shape >= 4))) return 0;
+    int n = max_n < s.max_n ? max_n : s.max_n;
+    if (n > kUpMaxN) n = kUpMaxN;
+    return n >= 2 ? n : 0;
+}
+
+size_t class_dyn_lds(int c, int shape, int max_n, int pot) {
+    const size_t n = (size_t)class_up_n(c, shape, max_n, pot);
+    return n * n * sizeof(double2) + n * (n > 0 ? n - 1 : 0) / 2 * sizeof(uint2);
+}
+
 hipError_t launch_plan(const int32_t* offset, int num, int max_n, const int32_t* active, Plan plan,
                        int32_t* status, hipStream_t st) {
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, st, offset, num, max_n, active, plan,
@@ -1006,8 +1065,11 @@ hipError_t launch_minimize_class(int mixed, int c, int shape, int grid, const Mi
                                  hipStream_t st) {
     const void* k = minimize_kernel_for(mixed, a.pot, c, shape);
     if (!k) return hipErrorInvalidValue;
-    void* args[] = {const_cast<MinArgs*>(&a)};
-    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, shape)), args, 0, st);
+    MinArgs b = a;
+    b.up_n = class_up_n(c, shape, a.max_n, a.pot);
+    void* args[] = {&b};
+    return hipLaunchKernel(k, dim3(grid), dim3(class_block(c, shape)), args,
+                           class_dyn_lds(c, shape, a.max_n, a.pot), st);
 }
 
 }  // namespace lj

@@ -120,6 +120,22 @@ def test_fp64_minimize_bitwise(sizes, rho):
             assert abs(r["energy"][k] - small[n]) < 1e-12
 
 
+@pytest.mark.parametrize("rho", [6.0, 3.0])
+def test_fp64_minimize_every_small_size_bitwise(rho):
+    """Every size 0 .. 44 in one batch: the one-wavefront kernel evaluates the
+    Morse pair over unique pairs up to 40 atoms (pair matrix in LDS, ordered
+    sums) and in the ordered loop above; both match the oracle bit for bit."""
+    sizes = list(range(0, 45))
+    off, x = random_starts(sizes, 870 + int(rho))
+    p = lj.lbfgs_params()
+    announce(f"morse minimize fp64 sizes=0..44 rho={rho}")
+    b, xd = morse_dev(off, x, rho)
+    r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    ro = O.minimize(off, x, oracle_params(p, rho))
+    for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k]), k
+
+
 @pytest.mark.parametrize("sizes,rho", [([13] * 8 + [38] * 8, 6.0), ([100, 150], 6.0)])
 def test_mixed_polish_reproduces_oracle_from_switch_point(sizes, rho):
     off, x = random_starts(sizes, 850 + len(sizes))
