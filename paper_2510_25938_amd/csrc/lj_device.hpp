@@ -77,20 +77,10 @@ __device__ __forceinline__ void swap_halves32(double v, double& lo, double& hi) 
     hi = *reinterpret_cast<double*>(&h);
 }
 
-// Row 0's value in every lane: row_bcast:15 copies lane 15 into row 1, then
-// row_bcast:31 copies lane 31 into rows 2 and 3.
-__device__ __forceinline__ double bcast_row0(double v) {
-    int2 b = *reinterpret_cast<int2*>(&v);
-    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, 0x142, 0x2, 0xF, false);
-    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, 0x142, 0x2, 0xF, false);
-    b.x = __builtin_amdgcn_update_dpp(b.x, b.x, 0x143, 0xC, 0xF, false);
-    b.y = __builtin_amdgcn_update_dpp(b.y, b.y, 0x143, 0xC, 0xF, false);
-    return *reinterpret_cast<double*>(&b);
-}
-
 // L = 64 leaves, or L = 16 when only lanes 0-15 can hold nonzero values (a
 // cluster of at most 16 atoms): then the sum is the tree of row 0 (the same
-// 16-leaf tree the pairwise sum pads N <= 16 to), broadcast to every lane.
+// 16-leaf tree the pairwise sum pads N <= 16 to), read from lane 0 as a
+// wavefront-uniform (scalar) value; branches on it are then scalar too.
 template <int L = kWave>
 __device__ __forceinline__ double wave_sum(double v) {
     static_assert(L == 16 || L == kWave, "16 or 64 leaves");
@@ -98,7 +88,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     v = v + dpp<kDppXor2>(v);
     v = v + dpp<kDppHalfMirror>(v);
     v = v + dpp<kDppMirror>(v);
-    if constexpr (L == 16) return bcast_row0(v);
+    if constexpr (L == 16) return uniform(v);
     double a, b;
     swap_rows16(v, a, b);  // a: even row's value in both rows, b: odd row's
     v = a + b;
@@ -199,7 +189,7 @@ __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp<kDppXor2>(v));
     v = fmax(v, dpp<kDppHalfMirror>(v));
     v = fmax(v, dpp<kDppMirror>(v));
-    if constexpr (L == 16) return bcast_row0(v);
+    if constexpr (L == 16) return uniform(v);
     double a, b;
     swap_rows16(v, a, b);
     v = fmax(a, b);
