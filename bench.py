@@ -603,6 +603,43 @@ def candidate_sweep(O, cands=(1, 2, 4, 8, 16), steps=30, seed=2510):
             "rows": rows}
 
 
+def iteration_cost(lj, inputs, torch, stream):
+    """Where an L-BFGS iteration's time goes when each cluster runs alone on
+    its SIMD: 8 clusters (one wavefront each, the rest of the chip idle) and
+    the full 1024-cluster LJ38 batch, FP64 and the FP32 phase of the mixed
+    path, with m = 10, 3 and 0 pairs of history and a tolerance no run reaches
+    (300-iteration cap).  From the slowest cluster's iterations and
+    evaluations: the two-loop cost per stored pair, (t(10) - t(3)) / 7, and a
+    fit of t = fixed + evaluations x cost per evaluation over m = 3 and m = 0
+    (steepest descent evaluates ~5 times per iteration)."""
+    out = {}
+    for n, count in ((13, 8), (38, 8), (38, 1024)):
+        sizes = np.full(count, n)
+        off, x = inputs.random_starts(sizes, inputs.SEED_BASE + 8)
+        b = lj.ClusterBatch(off)
+        xd = torch.from_numpy(x).cuda()
+        for prec in ("fp64", "mixed"):
+            rows = {}
+            for m in (10, 3, 0):
+                p = lj.lbfgs_params(m=m, gtol=1e-30, gtol_mixed_per_atom=1e-30, max_iter=300,
+                                    polish=0)
+                ms, r = timed(torch, stream, lambda _: lj.minimize(b, xd, p, prec, stream=stream))
+                it = int(r["iters"].max().item())
+                ev = int(r["evals"].max().item())
+                rows[m] = dict(ms=ms, iters_max=it, evals_max=ev,
+                               us_per_iteration=1e3 * ms / max(it, 1))
+            t10, t3, t0 = (rows[m]["us_per_iteration"] for m in (10, 3, 0))
+            e3 = rows[3]["evals_max"] / max(rows[3]["iters_max"], 1)
+            e0 = rows[0]["evals_max"] / max(rows[0]["iters_max"], 1)
+            pair = (t10 - t3) / 7.0
+            per_eval = (t0 - t3 + 3.0 * pair) / (e0 - e3) if e0 > e3 else None
+            fixed = t0 - e0 * per_eval if per_eval is not None else None
+            out[f"lj{n}x{count}_{prec}"] = dict(
+                by_history=rows, us_two_loop_per_pair=pair, us_per_evaluation=per_eval,
+                us_fixed_per_iteration=fixed)
+    return out
+
+
 def mixed_result_errors(lj, O, batch, starts, params, off, hm, stream, torch):
     """Error of every mixed-path result against the oracle (untimed).
 
@@ -639,7 +676,7 @@ def main():
     ap.add_argument("--no-pair", action="store_true", help="skip the standalone pair kernel")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other benchmark workloads")
-    ap.add_argument("--only", choices=["mixed", "fp64", "pair", *WORKLOADS],
+    ap.add_argument("--only", choices=["mixed", "fp64", "pair", "itercost", *WORKLOADS],
                     help="run one leg only and print its timing (for profiler runs)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run a plain 256 MiB device-to-device copy 5 times (calibrates the "
@@ -669,6 +706,12 @@ def main():
         stream.synchronize()
         print(json.dumps({"copy_ref_bytes_read": nbytes, "copy_ref_bytes_written": nbytes,
                           "launches": 5}), flush=True)
+        return
+    if args.only == "itercost":
+        from paper_2510_25938_amd import inputs as inputs_mod
+        print(json.dumps({"only": "itercost",
+                          "iteration_cost": iteration_cost(lj, inputs_mod, torch, stream)}),
+              flush=True)
         return
     if args.only in WORKLOADS:
         from paper_2510_25938_amd import inputs as inputs_mod
