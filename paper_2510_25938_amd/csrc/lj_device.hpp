@@ -19,7 +19,8 @@ constexpr int kMaxM = 10;   // L-BFGS history held per cluster (LJ_MAX_M)
 constexpr int kTileJ = 64;  // FP32 partner tile before a per-atom FP64 flush
 
 // ---------------------------------------------------------------------------
-// Wave-uniform broadcast of a value that every lane already holds.
+// Lane 0's value as a wavefront-uniform (scalar) value: a value that every
+// lane already holds, or a 16-leaf sum that row 0 holds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double uniform(double v) {
     int2 b = *reinterpret_cast<int2*>(&v);
