@@ -20,7 +20,7 @@ import torch
 from gpu_util import U32, announce, host, host_dict
 from oracle import oracle as O
 from paper_2510_25938_amd import lj
-from paper_2510_25938_amd.inputs import random_starts
+from paper_2510_25938_amd.inputs import random_starts, uniform_sizes
 
 pytestmark = pytest.mark.gpu
 
@@ -132,6 +132,55 @@ def test_fp64_minimize_every_small_size_bitwise(rho):
     b, xd = morse_dev(off, x, rho)
     r = host_dict(lj.minimize(b, xd, p, "fp64"))
     ro = O.minimize(off, x, oracle_params(p, rho))
+    for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k]), k
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_fp64_degenerate_clusters_unique_pairs(shape):
+    """Coincident atoms (a non-finite gradient), empty, one- and two-atom
+    clusters and a pair 1e7 apart beside ordinary ones, through the
+    one-wavefront kernels that evaluate the Morse pair over unique pairs
+    (64-lane and 16-lane reductions): every output equals the oracle's bit for
+    bit, NaNs included."""
+    sizes = [5, 0, 1, 2, 13, 16, 3, 9, 11]
+    off, x = random_starts(sizes, 880 + shape)
+    x = x.copy()
+    x[:, 1] = x[:, 0]                        # cluster 0: atoms 0 and 1 coincide
+    o = off[3]
+    x[:, o + 1] = x[:, o] + [1e7, 0.0, 0.0]  # cluster 3: a pair 1e7 apart
+    p = lj.lbfgs_params()
+    announce(f"morse degenerate clusters class-0 shape {shape}")
+    b, xd = morse_dev(off, x, 6.0)
+    ro = O.minimize(off, x, oracle_params(p, 6.0))
+    lj.set_schedule(lj.SCHED_MIN_CLASS[0], "fp64", b.max_n, shape)
+    try:
+        r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    finally:
+        lj.set_schedule(lj.SCHED_MIN_CLASS[0], "fp64", b.max_n, -1)
+    for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
+        assert np.array_equal(r[k], ro[k], equal_nan=True), k
+    assert r["status"][0] == lj.NONFINITE
+
+
+def test_fp64_autotuned_shapes_keep_parity(tmp_path):
+    """The autotuner on a Morse batch times the one-wavefront kernels with
+    their pair matrix in dynamic LDS beside the other shapes; whatever it
+    installs, the FP64 results stay bit-identical to the oracle."""
+    sizes = list(uniform_sizes(300, 2, 150, 8901))
+    off, x = random_starts(sizes, 8902)
+    b, xd = morse_dev(off, x, 6.0)
+    p = lj.lbfgs_params()
+    announce(f"morse autotune fp64 {b.num} clusters N 2..150")
+    try:
+        res = lj.autotune(b, xd, "fp64", cache=str(tmp_path / "sched.json"))
+        assert set(res["min_class"]) == {0, 1, 2}
+        r = host_dict(lj.minimize(b, xd, p, "fp64"))
+    finally:
+        for c in range(3):
+            lj.set_schedule(lj.SCHED_MIN_CLASS[c], "fp64", b.max_n, -1)
+        lj.set_schedule(lj.SCHED_EVAL, "fp64", b.max_n, *lj.eval_shape_default(b.max_n))
+    ro = O.minimize(off, x, oracle_params(p, 6.0))
     for k in ("xyz", "energy", "gnorm", "iters", "evals", "status"):
         assert np.array_equal(r[k], ro[k]), k
 
