@@ -20,12 +20,16 @@ pytestmark = pytest.mark.gpu
 KEYS = ("xyz", "energy", "gnorm", "iters", "evals", "status", "xyz_switch")
 
 
-def compare(sizes, seed, precision):
+def compare(sizes, seed, precision, pair="lj"):
     off, x = random_starts(sizes, seed)
-    b, xd = to_dev(off, x)
+    if pair == "lj":
+        b, xd = to_dev(off, x)
+    else:
+        b = lj.ClusterBatch(off, pair=pair, rho=6.0)
+        xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     p = lj.lbfgs_params()
     sw = precision == "mixed"
-    announce(f"noalloc {precision} clusters={len(sizes)} max_n={max(sizes)} seed={seed}")
+    announce(f"noalloc {precision} {pair} clusters={len(sizes)} max_n={max(sizes)} seed={seed}")
     ref = host_dict(lj.minimize(b, xd, p, precision, switch_point=sw))
     got = host_dict(lj.minimize_noalloc(b, xd, p, precision, switch_point=sw))
     for k in KEYS:
@@ -44,6 +48,14 @@ def test_noalloc_matches_workspace_entry_two_calls(precision):
     # second call, smaller: one class only, fewer clusters
     small = list(uniform_sizes(37, 2, 40, 7103))
     compare(small, 7104, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_noalloc_matches_workspace_entry_morse(precision):
+    """The Morse pair's one-wavefront kernels take their pair matrix in
+    dynamic LDS; the allocation-free entry launches them the same way."""
+    compare(list(uniform_sizes(300, 2, 40, 7106)), 7107, precision, pair="morse")
+    compare(list(uniform_sizes(21, 2, 16, 7108)), 7109, precision, pair="morse")
 
 
 def test_noalloc_rejects_over_limit_shapes():
