@@ -700,7 +700,7 @@ constexpr bool kUseTiles = W * A * kWave <= 2048 && !(W == 1 && A == 2);
 
 // A tile evaluates 32 ring distances per atom within itself, against n
 // partners per atom in the ordered loop: the tiles win above n = 32 (where a
-// one-wavefront cluster of at most 41 atoms takes the ring instead).
+// one-wavefront cluster of at most 43 atoms takes the ring instead).
 __device__ __forceinline__ bool tiles_for(int n) { return n > kWave / 2; }
 
 constexpr float kPadSpacing = 1.0e8f;
@@ -760,7 +760,7 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
 
 // ---------------------------------------------------------------------------
 // FP32 pair terms (Eq. (1) or the Morse pair) over unique pairs for
-// one-wavefront clusters of kRingMin <= n <= 41 atoms: a ring of period n.
+// one-wavefront clusters of kRingMin <= n <= 43 atoms: a ring of period n.
 // Lane l holds atom l mod n (lanes n .. 63 are replicas) and pairs with atom
 // (l + k) mod n for k = 1 .. n/2; for even n the distance n/2 is taken by the
 // lanes whose atom is below n/2 only, so every unique pair is evaluated once
@@ -770,20 +770,18 @@ __device__ __forceinline__ float3 tile_pair(const float4 pi, const float4* __res
 // (l + 1) mod n + k - 1 = l mod n + k, for every lane except 63, which wraps to
 // lane 0.  That one wrong value enters at lane 63 and moves down one lane per
 // step, so after K steps lanes 0 .. 63 - K are exact, and these include every
-// real lane when K <= 64 - n.  Steps run in groups of kRingGroup (padded steps
-// add zero but rotate); the result on lane l is the reaction on atom
+// real lane when K <= 64 - n.  Steps run in groups of kRingGroup, the last
+// group stopping at K; the result on lane l is the reaction on atom
 // (l + K) mod n, returned to its owner through LDS.  The coordinates are staged
-// as pos[j] = atom j mod n for j < 64 + K.  FP32 sums cover at most K <= 32
+// as pos[j] = atom j mod n for j < 64 + K.  FP32 sums cover at most K <= 21
 // terms and are added into FP64.  e_i follows the ordered-pair convention of
 // pairs_mixed, as in pairs_tiles.
 // ---------------------------------------------------------------------------
 constexpr int kRingGroup = 4;
 constexpr int kRingMin = 20;  // below, the ordered loop is as fast (staging and readout)
 
-// Steps of the ring for n atoms (n/2 rounded up to whole groups).
-__device__ __forceinline__ int ring_steps(int n) {
-    return (n / 2 + kRingGroup - 1) / kRingGroup * kRingGroup;
-}
+// Steps of the ring for n atoms: the distances 1 .. n/2.
+__device__ __forceinline__ int ring_steps(int n) { return n / 2; }
 __device__ __forceinline__ bool ring_for(int n) {
     return n >= kRingMin && ring_steps(n) <= kWave - n;
 }
@@ -795,19 +793,20 @@ __device__ __forceinline__ void ring_group(const float4 pi, const float4* __rest
                                            float& rx, float& ry, float& rz) {
     float4 p[kRingGroup];
 #pragma unroll
-    for (int u = 0; u < kRingGroup; ++u) p[u] = src[k0 + u];
+    for (int u = 0; u < kRingGroup; ++u) p[u] = src[LAST ? min(k0 + u, K) : k0 + u];
 #pragma unroll
     for (int u = 0; u < kRingGroup; ++u) {
+        // the last group stops at distance K (uniform); distance n/2 on the
+        // upper lanes adds nothing
+        bool skip = false;
+        if constexpr (LAST) {
+            if (k0 + u > K) break;
+            skip = k0 + u == K && upper;
+        }
         const float dx = pi.x - p[u].x;
         const float dy = pi.y - p[u].y;
         const float dz = pi.z - p[u].z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        // padded steps, and distance n/2 on the upper lanes, add nothing
-        bool skip = false;
-        if constexpr (LAST) {
-            const int k = k0 + u;
-            skip = k > K || (k == K && upper);
-        }
         float ep, f;
         if constexpr (POT == kPairMorse) {
             const float r = __builtin_amdgcn_sqrtf(r2);
@@ -838,8 +837,7 @@ __device__ __forceinline__ void pairs_ring(int n, const float4* __restrict__ pos
                                            float* __restrict__ rbuf, double& e,
                                            double (&g)[3][1], double rho) {
     const int lane = threadIdx.x;  // one wavefront
-    const int K = n / 2;
-    const int KS = ring_steps(n);
+    const int K = ring_steps(n);
     const int al = lane % n;
     const bool upper = (n % 2 == 0) && al >= K;
     const float rf = (float)rho, cf = -2.0f * rf;
@@ -851,11 +849,10 @@ __device__ __forceinline__ void pairs_ring(int n, const float4* __restrict__ pos
 #pragma unroll 1
     for (; k0 + kRingGroup - 1 < K; k0 += kRingGroup)
         ring_group<false, POT>(pi, src, k0, K, upper, rf, cf, te, tx, ty, tz, rx, ry, rz);
-#pragma unroll 1
-    for (; k0 <= KS; k0 += kRingGroup)
-        ring_group<true, POT>(pi, src, k0, K, upper, rf, cf, te, tx, ty, tz, rx, ry, rz);
-    if (lane < n) {  // lane l holds the reaction on atom (l + KS) mod n, KS < n
-        int t = lane + KS;
+    // the last group, with 1 .. kRingGroup of the distances (K >= 1)
+    ring_group<true, POT>(pi, src, k0, K, upper, rf, cf, te, tx, ty, tz, rx, ry, rz);
+    if (lane < n) {  // lane l holds the reaction on atom (l + K) mod n, K < n
+        int t = lane + K;
         if (t >= n) t -= n;
         rbuf[t] = rx;
         rbuf[kWave + t] = ry;

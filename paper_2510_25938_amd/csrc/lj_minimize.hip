@@ -175,7 +175,7 @@ struct Team {
 
     // E and g at x.  FP64: the ordered-pair loop in the oracle's order.
     // F32: FP32 pair arithmetic and per-atom FP32 partial sums, FP64 totals;
-    // the unique-pair ring for one-wavefront clusters of 20 to 41 atoms, the
+    // the unique-pair ring for one-wavefront clusters of 20 to 43 atoms, the
     // unique-pair 64-atom tiles above 32 atoms otherwise (Eq. (1)), else the
     // ordered loop.  Every loop reports e_i in the ordered-pair convention,
     // which counts each pair twice: E = 2 sum_i e_i for Eq. (1) (e_i holds

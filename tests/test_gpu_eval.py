@@ -192,12 +192,12 @@ def test_autotune_installs_a_valid_schedule(tmp_path):
     lj.set_schedule(lj.SCHED_EVAL, "mixed", 1000, *lj.eval_shape_default(1000))
 
 
-RING_SIZES = list(range(0, 65))  # ring n = 20 .. 41; ordered below, 64-atom tile above
+RING_SIZES = list(range(0, 65))  # ring n = 20 .. 43; ordered below, 64-atom tile above
 
 
 @pytest.mark.parametrize("sizes", [RING_SIZES[:33], RING_SIZES[33:]])
 def test_mixed_ring_across_sizes(sizes):
-    """The one-wavefront unique-pair FP32 ring (20 <= N <= 41, replicas in the
+    """The one-wavefront unique-pair FP32 ring (20 <= N <= 43, replicas in the
     lanes above N, a rotated reaction register) and its neighbours (the ordered
     loop below, the 64-atom tile above) for every N up to 64: within the
     a-priori bound, and Newton's third law to the FP32 accumulation bound."""

@@ -81,7 +81,7 @@ def test_mixed_error_bound(shape):
 @pytest.mark.parametrize("lo,hi,rho", [(0, 33, 6.0), (33, 65, 3.0)])
 def test_mixed_ring_across_sizes(lo, hi, rho):
     """Every N up to 64 for the Morse pair: the one-wavefront FP32 ring
-    (20 <= N <= 41) and the ordered loop around it, within the derived bound;
+    (20 <= N <= 43) and the ordered loop around it, within the derived bound;
     Newton's third law to the FP32 accumulation bound."""
     sizes = list(range(lo, hi))
     off, x = random_starts(sizes, 720 + lo)
